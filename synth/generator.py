@@ -1,0 +1,172 @@
+"""Seeded generator of piecewise-smooth test images and random masks.
+
+Recipe (one image):
+  1. uniform background grey ~ U[0, 1];
+  2. ``n_ellipses`` filled ellipses painted in order: centre uniform over the
+     image, semi-axes ~ U[0.05, 0.3] * min(H, W), angle ~ U[0, pi), grey ~ U[0, 1];
+  3. optionally ``0.75 * img + 0.25 * ramp`` with a linear ramp of random
+     direction rescaled to [0, 1];
+  4. additive N(0, noise_std^2) noise, then clipping to [0, 1];
+  5. a mask keeping exactly ``max(1, round(density * H * W))`` pixels drawn
+     uniformly without replacement.
+The unknown pixels of the initial guess hold the mean of the known values.
+Everything is drawn from ``numpy.random.default_rng(seed)`` in FP64 and cast
+to float32 / uint8 at the end.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    """A named synthetic workload: image shape(s), generator recipe and solver
+    parameters (contrast lambda, presmoothing sigma, step tau, FSI cycle
+    length n, cycle count M or relative stop tolerance)."""
+
+    name: str
+    H: int
+    W: int
+    n_ellipses: int
+    ramp: bool
+    noise_std: float
+    density: float
+    sigma: float
+    lam: float
+    tau: float
+    n: int
+    M: int
+    tol: float = 0.0
+    B: int = 1
+    seed_base: int = 0
+
+
+WORKLOADS = {
+    # 64x64, 5 ellipses, 5% mask; the oracle finishes it in seconds.
+    "small64": Workload("small64", 64, 64, 5, False, 0.01, 0.05,
+                        sigma=1.0, lam=0.05, tau=0.05, n=10, M=20,
+                        seed_base=1000),
+    # 512x512, 30 ellipses + ramp, 4% mask, run to relative residual < 1e-4.
+    "single512": Workload("single512", 512, 512, 30, True, 0.01, 0.04,
+                          sigma=1.5, lam=0.03, tau=0.05, n=40, M=400,
+                          tol=1e-4, seed_base=2000),
+    # 4096x4096, 200 ellipses + ramp, 3% mask, 100 cycles of 15 steps.
+    "large4096": Workload("large4096", 4096, 4096, 200, True, 0.005, 0.03,
+                          sigma=2.0, lam=0.02, tau=0.05, n=15, M=100,
+                          seed_base=3000),
+    # 64 images of uneven size (sides U{128..1024}), 2..8% masks.
+    "batch64": Workload("batch64", 0, 0, 30, True, 0.005, 0.05,
+                        sigma=1.5, lam=0.03, tau=0.05, n=15, M=40, B=64,
+                        seed_base=4000),
+    # 16 images of 256x256, 4% mask; tonal optimisation through 30 cycles.
+    "adjoint16": Workload("adjoint16", 256, 256, 30, True, 0.01, 0.04,
+                          sigma=1.0, lam=0.05, tau=0.05, n=10, M=30, B=16,
+                          seed_base=5000),
+}
+
+
+def make_image(H: int, W: int, n_ellipses: int, ramp: bool, noise_std: float,
+               rng: np.random.Generator) -> np.ndarray:
+    """Draw one piecewise-smooth image in FP64 with values in [0, 1]."""
+    img = np.full((H, W), rng.uniform(0.0, 1.0), dtype=np.float64)
+    m = float(min(H, W))
+    for _ in range(n_ellipses):
+        cy = rng.uniform(0.0, H)
+        cx = rng.uniform(0.0, W)
+        a = rng.uniform(0.05, 0.3) * m
+        b = rng.uniform(0.05, 0.3) * m
+        th = rng.uniform(0.0, np.pi)
+        grey = rng.uniform(0.0, 1.0)
+        rad = max(a, b)
+        y0, y1 = max(0, int(np.floor(cy - rad))), min(H, int(np.ceil(cy + rad)) + 1)
+        x0, x1 = max(0, int(np.floor(cx - rad))), min(W, int(np.ceil(cx + rad)) + 1)
+        if y0 >= y1 or x0 >= x1:
+            continue
+        yy = np.arange(y0, y1, dtype=np.float64)[:, None] - cy
+        xx = np.arange(x0, x1, dtype=np.float64)[None, :] - cx
+        c, s = np.cos(th), np.sin(th)
+        p = (xx * c + yy * s) / a
+        q = (-xx * s + yy * c) / b
+        inside = p * p + q * q <= 1.0
+        img[y0:y1, x0:x1][inside] = grey
+    if ramp:
+        phi = rng.uniform(0.0, 2.0 * np.pi)
+        yy = np.arange(H, dtype=np.float64)[:, None]
+        xx = np.arange(W, dtype=np.float64)[None, :]
+        r = xx * np.cos(phi) / W + yy * np.sin(phi) / H
+        lo, hi = r.min(), r.max()
+        r = (r - lo) / (hi - lo) if hi > lo else np.zeros_like(r)
+        img = 0.75 * img + 0.25 * r
+    if noise_std > 0:
+        img = img + rng.normal(0.0, noise_std, size=(H, W))
+    return np.clip(img, 0.0, 1.0)
+
+
+def make_mask(H: int, W: int, density: float, rng: np.random.Generator) -> np.ndarray:
+    """Exact-count uniform random mask (uint8, 1 = known)."""
+    count = max(1, int(round(density * H * W)))
+    count = min(count, H * W)
+    idx = rng.choice(H * W, size=count, replace=False)
+    mask = np.zeros(H * W, dtype=np.uint8)
+    mask[idx] = 1
+    return mask.reshape(H, W)
+
+
+def _initial_guess(img: np.ndarray, mask: np.ndarray) -> np.ndarray:
+    known = img[mask != 0]
+    fill = float(known.mean()) if known.size else 0.5
+    u0 = np.where(mask != 0, img, fill)
+    return u0
+
+
+def make_problem(H: int, W: int, n_ellipses: int, ramp: bool, noise_std: float,
+                 density: float, seed: int) -> dict:
+    """One inpainting problem: ground truth ``image``, ``mask`` (u8), ``known``
+    (image on the mask, 0 elsewhere) and ``u_init`` (known values on the mask,
+    mean of the known values elsewhere), all float32 except the mask."""
+    rng = np.random.default_rng(seed)
+    img = make_image(H, W, n_ellipses, ramp, noise_std, rng)
+    mask = make_mask(H, W, density, rng)
+    known = np.where(mask != 0, img, 0.0)
+    u0 = _initial_guess(img, mask)
+    return {
+        "image": img.astype(np.float32),
+        "mask": mask,
+        "known": known.astype(np.float32),
+        "u_init": u0.astype(np.float32),
+        "seed": seed,
+    }
+
+
+def make_batch(wl: Workload, B: Optional[int] = None,
+               shape: Optional[Tuple[int, int]] = None) -> dict:
+    """Equal-size batch for workload ``wl`` (arrays shaped [B, H, W]);
+    image i uses seed ``wl.seed_base + i``."""
+    B = wl.B if B is None else B
+    H, W = (wl.H, wl.W) if shape is None else shape
+    probs = [make_problem(H, W, wl.n_ellipses, wl.ramp, wl.noise_std,
+                          wl.density, wl.seed_base + i) for i in range(B)]
+    return {k: np.stack([p[k] for p in probs]) for k in ("image", "mask", "known", "u_init")}
+
+
+def make_uneven_batch(wl: Workload, B: Optional[int] = None,
+                      side_range: Tuple[int, int] = (128, 1024),
+                      density_range: Tuple[float, float] = (0.02, 0.08)) -> List[dict]:
+    """Uneven batch: image i has H, W ~ U{side_range} independently and mask
+    density ~ U[density_range], drawn from ``default_rng(wl.seed_base)``; the
+    image itself is drawn from seed ``wl.seed_base + 1 + i``."""
+    B = wl.B if B is None else B
+    rng = np.random.default_rng(wl.seed_base)
+    out = []
+    for i in range(B):
+        H = int(rng.integers(side_range[0], side_range[1] + 1))
+        W = int(rng.integers(side_range[0], side_range[1] + 1))
+        dens = float(rng.uniform(*density_range))
+        p = make_problem(H, W, wl.n_ellipses, wl.ramp, wl.noise_std, dens,
+                         wl.seed_base + 1 + i)
+        p["density"] = dens
+        out.append(p)
+    return out
