@@ -1,0 +1,249 @@
+#!/usr/bin/env python3
+"""Throughput of fourth-order EED inpainting with FSI on one MI355X.
+
+A timed "step" is one FSI cycle (n fused inner steps plus the FP64 residual)
+over the 4096 x 4096 synthetic workload (200 ellipses + ramp + noise, 3%
+mask, sigma 2, lambda 0.02, tau 0.05, n 15), run through eed4_inpaint with
+the cycle replayed as a hipGraph.  Inputs are resident in HBM before timing.
+
+The JSON line carries:
+  value      pixel-updates/s of the whole timed region (Mpixel-updates/s)
+  roofline   the fused step kernel: algorithmic bytes per launch (13 B per
+             pixel-update: read u^k, read u^{k-1}, write u^{k+1}, read the
+             u8 mask) over its average launch time, measured here with HIP
+             events around back-to-back eed4_fsi_step launches on the same
+             stream, against the 8 TB/s HBM peak; traffic from the committed
+             rocprofv3 counter summary when it matches the current kernel
+  cpu_baseline  the FP64 oracle on the host cores, one cycle of the same image
+  adjoint_forward_ratio  backward/forward time on 16 x 256 x 256 (30 cycles of 10)
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+BYTES_PER_UPDATE = 13          # 4 (u^k) + 4 (u^{k-1}) + 4 (u^{k+1}) + 1 (mask)
+HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
+KERNEL_SOURCES = ("paper_2006_10406_amd/csrc/eed4_tile.h",
+                  "paper_2006_10406_amd/csrc/eed4_forward.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_large4096_traffic.json")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(updates_per_launch):
+    """HBM bytes per launch from the committed counter summary, or None when it
+    is missing or was taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha") != kernel_source_sha():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(pr, wl):
+    import oracle
+    n = wl.n
+    t0 = time.perf_counter()
+    oracle.inpaint(pr["u_init"], pr["mask"], pr["known"], wl.lam, wl.sigma, wl.tau, n, 1)
+    dt = time.perf_counter() - t0
+    upd = pr["u_init"].size * n
+    return {"value": upd / dt / 1e6, "unit": "Mpixel-updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"one FSI cycle ({n} steps) of the full {wl.H}x{wl.W} workload image, "
+                      f"FP64, {dt:.1f} s"}
+
+
+def adjoint_ratio(eed4, torch, args):
+    """Forward (with per-cycle checkpoints) vs backward time on 16 x 256 x 256."""
+    from synth import WORKLOADS, make_batch
+    wl = WORKLOADS["adjoint16"]
+    b = make_batch(wl)
+    dev = "cuda"
+    u0 = torch.from_numpy(b["u_init"]).to(dev)
+    mask = torch.from_numpy(b["mask"]).to(dev)
+    known = torch.from_numpy(b["known"]).to(dev)
+    B, H, W = u0.shape
+    p = eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, wl.M)
+    ck = torch.empty((wl.M, B, H, W), dtype=torch.float32, device=dev)
+    gu = torch.randn((B, H, W), device=dev) * 1e-3
+    gk = torch.empty_like(gu)
+    gi = torch.empty_like(gu)
+    gl = torch.empty(B, device=dev)
+    wsf = torch.empty(eed4.eed4_workspace_size(eed4.EED4_OP_INPAINT, B, H, W, p) + 256,
+                      dtype=torch.uint8, device=dev)
+    wsb = torch.empty(eed4.eed4_workspace_size(eed4.EED4_OP_BACKWARD, B, H, W, p) + 256,
+                      dtype=torch.uint8, device=dev)
+
+    def fwd():
+        u = u0.clone()
+        eed4.eed4_inpaint(u, mask, known, p, ckpt=ck)
+
+    def bwd():
+        eed4.eed4_backward(ck, mask, known, p, wl.M, gu, gk, gi, gl)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    tf = timed(fwd, 3)
+    tb = timed(bwd, 3)
+    upd = B * H * W * wl.n * wl.M
+    return {"forward_ms": tf, "backward_ms": tb, "ratio": tb / tf,
+            "forward_mpix_updates_s": upd / (tf * 1e-3) / 1e6,
+            "workload": f"adjoint16: {B} x {H}x{W}, {wl.M} cycles of {wl.n}, checkpoint per cycle"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100, help="timed FSI cycles")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed FSI cycles")
+    ap.add_argument("--kernel-reps", type=int, default=20,
+                    help="cycles of back-to-back eed4_fsi_step launches for the roofline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the path has no multi-GPU decomposition)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2006_10406_amd as eed4
+    from synth import WORKLOADS, make_problem
+
+    wl = WORKLOADS["large4096"]
+    log(f"generating {wl.name} {wl.H}x{wl.W}")
+    pr = make_problem(wl.H, wl.W, wl.n_ellipses, wl.ramp, wl.noise_std, wl.density, wl.seed_base)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    u_init = torch.from_numpy(pr["u_init"]).to(dev)
+    mask = torch.from_numpy(pr["mask"]).to(dev)
+    known = torch.from_numpy(pr["known"]).to(dev)
+    H, W, n = wl.H, wl.W, wl.n
+    pw = eed4.params(wl.lam, wl.sigma, wl.tau, n, max(args.warmup, 1))
+    pt = eed4.params(wl.lam, wl.sigma, wl.tau, n, args.steps)
+    ws = torch.empty(eed4.eed4_workspace_size(eed4.EED4_OP_INPAINT, 1, H, W, pt) + 256,
+                     dtype=torch.uint8, device=dev)
+    wsv = ws[(-ws.data_ptr()) % 256:]
+
+    # ---- whole-path timing: warmup cycles, then exactly K timed cycles ----
+    u = u_init.clone()
+    log(f"warmup {args.warmup} cycles")
+    eed4.eed4_inpaint(u, mask, known, pw, ws=wsv)
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} cycles of {n} steps")
+    stream = torch.cuda.current_stream(dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    st, _ = eed4.eed4_inpaint(u, mask, known, pt, ws=wsv, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    sec = ms * 1e-3
+    updates = H * W * n * args.steps
+    value = updates / sec / 1e6
+    log(f"{st.cycles} cycles, {ms:.2f} ms (wall {wall * 1e3:.2f} ms), {value:.0f} Mpix-upd/s")
+
+    # ---- kernel timing: back-to-back fused step launches on the same stream ----
+    a = u.clone()
+    b = u.clone()
+    c = u.clone()
+    e2 = torch.cuda.Event(enable_timing=True)
+    e3 = torch.cuda.Event(enable_timing=True)
+    ps = eed4.params(wl.lam, wl.sigma, wl.tau, n, 1)
+    eed4.eed4_fsi_step(a, a, b, mask, ps, 0, stream=stream)  # warm
+    torch.cuda.synchronize()
+    def roles(k):  # same rotation as a cycle: S=a, X=b, Y=c
+        if k == 0:
+            return a, a, b
+        if k == 1:
+            return b, a, c
+        return (b, c, c) if k % 2 else (c, b, b)
+
+    launches = 0
+    e2.record(stream)
+    for _ in range(args.kernel_reps):
+        for k in range(n):
+            cur, prev, out = roles(k)
+            eed4.eed4_fsi_step(cur, prev, out, mask, ps, k, stream=stream)
+            launches += 1
+    e3.record(stream)
+    torch.cuda.synchronize()
+    kms = e2.elapsed_time(e3) / launches
+    per_launch_bytes = BYTES_PER_UPDATE * H * W
+    achieved = per_launch_bytes / (kms * 1e-3) / 1e9
+    traffic = measured_traffic(H * W)
+    log(f"fused step kernel: {kms * 1e3:.1f} us/launch, {achieved:.0f} GB/s algorithmic")
+
+    out = {
+        "metric": "Mpixel-updates/s of fused 4th-order EED FSI step + adjoint/forward time ratio",
+        "value": round(value, 1),
+        "unit": "Mpixel-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "large4096", "H": H, "W": W, "batch": 1, "sigma": wl.sigma,
+                   "lambda": wl.lam, "tau": wl.tau, "cycle_len": n, "mask_density": wl.density,
+                   "step": "one FSI cycle (15 fused inner steps + FP64 residual)",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "step_kernel<6,64,32>",
+                     "kernel_us": round(kms * 1e3, 2),
+                     "algorithmic_bytes_per_launch": per_launch_bytes,
+                     "kernel_source_sha": kernel_source_sha()},
+    }
+    if not args.no_adjoint:
+        try:
+            out["adjoint_forward_ratio"] = adjoint_ratio(eed4, torch, args)
+        except eed4.EED4Error as ex:
+            log(f"adjoint ratio unavailable: {ex}")
+            out["adjoint_forward_ratio"] = None
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on the host (one cycle)")
+        out["cpu_baseline"] = cpu_baseline(pr, wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,181 @@
+/*
+ * eed4.h -- C ABI of the MI355X (gfx950) implementation of fourth-order
+ * edge-enhancing diffusion (FOEED) inpainting with the Fast Semi-Iterative
+ * (FSI) scheme, after Jumakulyyev & Schultz, "Fourth-Order Anisotropic
+ * Diffusion for Inpainting and Image Compression" (arXiv 2006.10406).
+ *
+ * The problem (Sec. 2.1, eq. inpaintingModel; Sec. 3.1, eq. genModel):
+ *   du/dt = -d_ij [ D(J(u_sigma)) : H(u) ]_ij  on the unknown pixels,
+ *   u = f on the known set K, homogeneous Neumann condition on the border,
+ * with the fourth-order diffusion tensor D built from the Gaussian-presmoothed
+ * gradient (eigenvalues g, 1, sqrt(g), 0; Charbonnier g, eq. CharDiff), solved
+ * to steady state with FSI cycles (Sec. 3.3):
+ *   u^{m,k+1} = alpha_k (I - tau P(u^{m,k})) u^{m,k} + (1 - alpha_k) u^{m,k-1},
+ *   alpha_k = (4k+2)/(2k+3), u^{m,-1} := u^{m,0}, u^{m+1,0} := u^{m,n}.
+ *
+ * Conventions shared by every entry point
+ *  - Images are row-major float32 [H][W] (x = column, fastest; y = row);
+ *    a batch is [B][H][W] of equal-size images, contiguous.
+ *  - The mask is uint8 [B][H][W]; nonzero marks a known pixel.  known holds
+ *    f and is read only where the mask is nonzero.
+ *  - Every array pointer is a DEVICE pointer owned by the caller.  The library
+ *    never frees or retains caller memory and allocates no device memory: the
+ *    caller passes a workspace of at least eed4_workspace_size() bytes
+ *    (256-byte aligned), used as scratch for the duration of the call.
+ *  - stream is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *    is stream-ordered; only eed4_inpaint and eed4_inpaint_batched
+ *    synchronise (once per cycle when a tolerance is set, else once at the
+ *    end) to read residuals.
+ *  - Return value: EED4_OK (0) or a negative EED4_E* code; no exception
+ *    crosses the ABI.  eed4_strerror() gives a message (including the last
+ *    HIP error for EED4_EHIP).
+ *  - Numerics: FP32 arithmetic on the device; the cycle residual is
+ *    accumulated in FP64.  Results are deterministic (no atomics in any sum).
+ *  - Readings of the paper fixed by this ABI: half-sample mirror boundary,
+ *    sampled Gaussian truncated at radius ceil(3 sigma) <= 8, central
+ *    differences for the gradient, sign-corrected mixed difference u_xy
+ *    (Sec. 3.3 prints four plus signs), tensor recomputed at every step.
+ */
+#ifndef EED4_H
+#define EED4_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---- */
+#define EED4_OK          0
+#define EED4_EINVAL     (-1)  /* bad size, pointer or parameter              */
+#define EED4_EUNSTABLE  (-2)  /* tau outside (0, 1/16] without the override */
+#define EED4_EWORKSPACE (-3)  /* workspace missing, misaligned or too small  */
+#define EED4_EHIP       (-4)  /* a HIP runtime call or kernel launch failed  */
+#define EED4_EDIVERGED  (-5)  /* non-finite cycle residual                   */
+
+/* ---- flags (eed4_params.flags) ---- */
+/* Accept tau > 1/16.  The explicit step is L2-stable for tau <= 1/16 because
+ * the largest eigenvalue of P is at most 32 (Sec. 3.3 gives the sufficient
+ * bound 1/17 and reports 0.066 as usable in practice). */
+#define EED4_ALLOW_LARGE_TAU 0x1
+/* Stop on the plain residual ||u^{m,n} - u^{m,0}||_2 < tol (as in Sec. 3.3)
+ * instead of the relative one ||u^{m,n} - u^{m,0}||_2 / ||u^{m,n}||_2. */
+#define EED4_ABS_TOL         0x2
+/* Launch each inner step directly instead of replaying a captured hipGraph
+ * of the cycle (same results; for comparison). */
+#define EED4_NO_GRAPH        0x4
+
+/* ---- workspace sizing (eed4_workspace_size op) ---- */
+#define EED4_OP_INPAINT  1
+#define EED4_OP_CYCLE    2
+#define EED4_OP_BACKWARD 3
+
+typedef struct eed4_params {
+    float lambda;    /* contrast lambda > 0 of the Charbonnier diffusivity
+                        g(s^2) = 1/sqrt(1 + s^2/lambda^2) (eq. CharDiff)        */
+    float sigma;     /* presmoothing sigma >= 0 with ceil(3 sigma) <= 8; 0 disables
+                        the presmoothing (Sec. 2.2)                            */
+    float tau;       /* time step tau in (0, 1/16] (Sec. 3.3)                   */
+    int   cycle_len; /* FSI cycle length n >= 1 (the paper uses 40)             */
+    int   max_cycles;/* cycle count M >= 1 (upper bound when tol > 0)           */
+    float tol;       /* >= 0; > 0 stops after the first cycle whose residual is
+                        below tol for every image of the batch (Sec. 3.3)       */
+    int   flags;     /* EED4_* flags                                           */
+} eed4_params;
+
+typedef struct eed4_stats {
+    int    cycles;        /* cycles run                                         */
+    double residual;      /* largest ||u^{m,n} - u^{m,0}||_2 over the batch,
+                             last cycle                                         */
+    double rel_residual;  /* largest relative residual over the batch           */
+} eed4_stats;
+
+/* One image of an uneven batch (eed4_inpaint_batched).  Device pointers. */
+typedef struct eed4_image {
+    float         *u;       /* [H][W] in: initial guess, out: result            */
+    const uint8_t *mask;    /* [H][W] nonzero = known                           */
+    const float   *known;   /* [H][W] f, read where mask != 0                   */
+    int            H, W;    /* >= 1                                             */
+    float          lambda;  /* per-image contrast (> 0)                         */
+} eed4_image;
+
+/* Gaussian truncation radius ceil(3 sigma), evaluated in double from the
+ * float sigma, used by every entry point (0 for sigma == 0); -1 if sigma is
+ * negative, not finite or the radius would exceed 8. */
+int eed4_radius(float sigma);
+
+/* Bytes of workspace needed by op (EED4_OP_*) for a batch of B images of
+ * H x W; max_cycles of p matters for EED4_OP_INPAINT (residual history) and
+ * cycle_len for EED4_OP_BACKWARD (recomputed states).  0 on invalid input. */
+size_t eed4_workspace_size(int op, int B, int H, int W, const eed4_params *p);
+
+/* Inpaint B equal-size images (Sec. 2.1 model with the tensor of Sec. 3.1,
+ * solved by FSI, Sec. 3.3).
+ *  u      [B][H][W] in: initial guess (any values off the mask); out: u^{m,0}
+ *         after the last cycle run.  Known pixels are set to f first.
+ *  ckpt   NULL, or [max_cycles][B][H][W]: receives the cycle-start state
+ *         u^{m,0} of every cycle run (for eed4_backward).
+ *  hist   NULL, or HOST [max_cycles][B][2]: per cycle and image, the residual
+ *         ||u^{m,n}-u^{m,0}||_2 and ||u^{m,n}||_2 (FP64).
+ *  stats  NULL or HOST output.
+ * Errors: EED4_EINVAL, EED4_EUNSTABLE, EED4_EWORKSPACE, EED4_EHIP,
+ * EED4_EDIVERGED (u then holds the diverged state). */
+int eed4_inpaint(float *u, const uint8_t *mask, const float *known,
+                 int B, int H, int W, const eed4_params *p, float *ckpt,
+                 void *ws, size_t ws_bytes, void *stream,
+                 eed4_stats *stats, double *hist);
+
+/* One FSI cycle (n = p->cycle_len inner steps, Sec. 3.3) in place on u,
+ * after setting the known pixels to f.  d_sums: DEVICE [B][2] receives
+ * sum (u^{m,n}-u^{m,0})^2 and sum (u^{m,n})^2 per image (FP64).  No
+ * synchronisation, no stop decision.  max_cycles and tol are ignored. */
+int eed4_fsi_cycle(float *u, const uint8_t *mask, const float *known,
+                   int B, int H, int W, const eed4_params *p,
+                   void *ws, size_t ws_bytes, void *stream, double *d_sums);
+
+/* One FSI inner step (Sec. 3.3) of B equal-size images:
+ *   uout = alpha_k (I - tau P(ucur)) ucur + (1 - alpha_k) uprev,
+ * then uout = ucur on the known pixels (ucur must already hold f there).
+ * alpha_k = (4k+2)/(2k+3) with k >= 0 the step index inside the cycle.
+ * uout may equal uprev (each pixel is read before it is written) but must not
+ * overlap ucur.  No workspace, no residual, no synchronisation. */
+int eed4_fsi_step(const float *ucur, const float *uprev, float *uout,
+                  const uint8_t *mask, int B, int H, int W,
+                  const eed4_params *p, int k, void *stream);
+
+/* Adjoint of eed4_inpaint run for exactly M cycles with tol == 0 (the FSI
+ * evolution differentiated by hand; the paper gives the forward scheme only).
+ * Each cycle is recomputed from its checkpoint, then reversed step by step.
+ *  ckpt        [M][B][H][W] cycle-start states as written by eed4_inpaint.
+ *  grad_u      [B][H][W] dL/du^{M,0}.
+ *  grad_known  [B][H][W] out: dL/df (0 off the mask).
+ *  grad_init   [B][H][W] out: dL/du_init (0 on the mask).
+ *  grad_lambda [B] out: dL/dlambda contributed by each image (float).
+ * max_cycles and tol of p are ignored; M is passed explicitly. */
+int eed4_backward(const float *ckpt, const uint8_t *mask, const float *known,
+                  int B, int H, int W, const eed4_params *p, int M,
+                  const float *grad_u, float *grad_known, float *grad_init,
+                  float *grad_lambda, void *ws, size_t ws_bytes, void *stream);
+
+/* Bytes of workspace for eed4_inpaint_batched over the given images. */
+size_t eed4_batched_workspace_size(const eed4_image *imgs, int B,
+                                   const eed4_params *p);
+
+/* Inpaint B images of uneven sizes with one persistent launch per inner step
+ * over a tile work-queue spanning all images; the cycle is replayed as a
+ * captured hipGraph.  sigma, tau, n, M, tol and flags come from p; lambda
+ * from each image.  imgs is a HOST array.  stats: NULL or HOST [B]; an image
+ * whose residual falls below tol stops and leaves the queue (per-image stop).
+ * Results equal eed4_inpaint on each image alone. */
+int eed4_inpaint_batched(const eed4_image *imgs, int B, const eed4_params *p,
+                         void *ws, size_t ws_bytes, void *stream,
+                         eed4_stats *stats);
+
+/* Message for a return code. */
+const char *eed4_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EED4_H */

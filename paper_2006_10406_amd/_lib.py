@@ -1,0 +1,81 @@
+"""ctypes view of ``include/eed4.h``.  Loading fails loudly when the HIP
+library has not been built: there is no fallback path."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libeed4.so")
+
+EED4_OK = 0
+EED4_EINVAL = -1
+EED4_EUNSTABLE = -2
+EED4_EWORKSPACE = -3
+EED4_EHIP = -4
+EED4_EDIVERGED = -5
+
+EED4_ALLOW_LARGE_TAU = 0x1
+EED4_ABS_TOL = 0x2
+EED4_NO_GRAPH = 0x4
+
+EED4_OP_INPAINT = 1
+EED4_OP_CYCLE = 2
+EED4_OP_BACKWARD = 3
+
+EXPORTED = ("eed4_radius", "eed4_workspace_size", "eed4_inpaint", "eed4_fsi_cycle",
+            "eed4_fsi_step",
+            "eed4_backward", "eed4_batched_workspace_size", "eed4_inpaint_batched",
+            "eed4_strerror")
+
+
+class eed4_params(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_float), ("sigma", ctypes.c_float), ("tau", ctypes.c_float),
+                ("cycle_len", ctypes.c_int), ("max_cycles", ctypes.c_int),
+                ("tol", ctypes.c_float), ("flags", ctypes.c_int)]
+
+
+class eed4_stats(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int), ("residual", ctypes.c_double),
+                ("rel_residual", ctypes.c_double)]
+
+
+class eed4_image(ctypes.Structure):
+    _fields_ = [("u", ctypes.c_void_p), ("mask", ctypes.c_void_p), ("known", ctypes.c_void_p),
+                ("H", ctypes.c_int), ("W", ctypes.c_int), ("lambda_", ctypes.c_float)]
+
+
+_L = None
+
+
+def lib():
+    global _L
+    if _L is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                              "(python -c 'import __graft_entry__ as g; g.build()')")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz, i, f = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_float
+        pp = ctypes.POINTER(eed4_params)
+        L.eed4_radius.restype = i
+        L.eed4_radius.argtypes = [f]
+        L.eed4_workspace_size.restype = sz
+        L.eed4_workspace_size.argtypes = [i, i, i, i, pp]
+        L.eed4_inpaint.restype = i
+        L.eed4_inpaint.argtypes = [vp, vp, vp, i, i, i, pp, vp, vp, sz, vp,
+                                   ctypes.POINTER(eed4_stats), vp]
+        L.eed4_fsi_cycle.restype = i
+        L.eed4_fsi_cycle.argtypes = [vp, vp, vp, i, i, i, pp, vp, sz, vp, vp]
+        L.eed4_fsi_step.restype = i
+        L.eed4_fsi_step.argtypes = [vp, vp, vp, vp, i, i, i, pp, i, vp]
+        L.eed4_backward.restype = i
+        L.eed4_backward.argtypes = [vp, vp, vp, i, i, i, pp, i, vp, vp, vp, vp, vp, sz, vp]
+        L.eed4_batched_workspace_size.restype = sz
+        L.eed4_batched_workspace_size.argtypes = [ctypes.POINTER(eed4_image), i, pp]
+        L.eed4_inpaint_batched.restype = i
+        L.eed4_inpaint_batched.argtypes = [ctypes.POINTER(eed4_image), i, pp, vp, sz, vp,
+                                           ctypes.POINTER(eed4_stats)]
+        L.eed4_strerror.restype = ctypes.c_char_p
+        L.eed4_strerror.argtypes = [i]
+        _L = L
+    return _L

@@ -1,0 +1,325 @@
+// Host side of libeed4: argument checks, workspace layout, the FSI cycle
+// driver (buffer rotation, hipGraph capture and replay, residual read-back
+// and stop rule) and the C ABI entry points declared in include/eed4.h.
+#include "eed4.h"
+#include "eed4_internal.h"
+#include "eed4_host.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+namespace eed4 {
+
+thread_local std::string g_last_hip;
+
+int hip_fail(hipError_t e, const char *where)
+{
+    g_last_hip = std::string(where) + ": " + hipGetErrorString(e);
+    return EED4_EHIP;
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int check_params(const eed4_params *p, int B, int H, int W)
+{
+    if (!p || B < 1 || H < 1 || W < 1) return EED4_EINVAL;
+    if (H > (1 << 24) || W > (1 << 24)) return EED4_EINVAL;
+    if ((long long)H * W > (1LL << 31) || (long long)B * H * W > (1LL << 36)) return EED4_EINVAL;
+    if (!(p->lambda > 0.0f) || !std::isfinite(p->lambda)) return EED4_EINVAL;
+    if (eed4_radius(p->sigma) < 0) return EED4_EINVAL;
+    if (!(p->tau > 0.0f) || !std::isfinite(p->tau)) return EED4_EINVAL;
+    if (p->cycle_len < 1 || p->max_cycles < 1) return EED4_EINVAL;
+    if (!(p->tol >= 0.0f) || !std::isfinite(p->tol)) return EED4_EINVAL;
+    if (!(p->flags & EED4_ALLOW_LARGE_TAU) && (double)p->tau > 1.0 / 16.0) return EED4_EUNSTABLE;
+    return EED4_OK;
+}
+
+StepArgs make_args(float sigma, int R, float tau, float lambda, int k)
+{
+    StepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    if (R == 0) {
+        a.w[0] = 1.0f;
+    } else {
+        double s = (double)sigma, w[2 * kRMax + 1], sum = 0.0;
+        for (int j = -R; j <= R; ++j) {
+            w[j + R] = std::exp(-(double)(j * j) / (2.0 * s * s));
+            sum += w[j + R];
+        }
+        for (int j = 0; j <= 2 * R; ++j) a.w[j] = (float)(w[j] / sum);
+    }
+    a.tau = tau;
+    a.alpha = (float)((4.0 * k + 2.0) / (2.0 * k + 3.0));
+    a.inv_lam2 = (float)(1.0 / ((double)lambda * (double)lambda));
+    return a;
+}
+
+hipStream_t capture_stream()
+{
+    static std::mutex mu;
+    static std::vector<hipStream_t> streams;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)streams.size() <= dev) streams.resize(dev + 1, nullptr);
+    if (!streams[dev]) {
+        hipStream_t s = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+        streams[dev] = s;
+    }
+    return streams[dev];
+}
+
+// Rotation of the three state buffers over one cycle: S (cycle start and
+// result), X, Y.  Step k reads cur = u^k (with halo) and prev = u^{k-1}
+// (pointwise) and writes out = u^{k+1}; out may alias prev because both are
+// touched only at the thread's own pixel.  The last step writes S while
+// reading S pointwise for the residual.
+void cycle_roles(int k, int n, float *S, float *X, float *Y, float **cur, float **prev,
+                 float **out)
+{
+    if (k == 0) {
+        *cur = S; *prev = S; *out = X;
+    } else {
+        *cur = (k & 1) ? X : Y;
+        *prev = (k == 1) ? S : ((k & 1) ? Y : X);
+        *out = (k & 1) ? Y : X;
+    }
+    if (k == n - 1 && n > 1) *out = S;
+}
+
+int enqueue_cycle(const CycleJob &j, hipStream_t s)
+{
+    const int n = j.n;
+    for (int k = 0; k < n; ++k) {
+        float *cur, *prev, *out;
+        cycle_roles(k, n, j.S, j.X, j.Y, &cur, &prev, &out);
+        const bool last = (k == n - 1);
+        StepArgs a = make_args(j.sigma, j.R, j.tau, j.lambda, k);
+        hipError_t e = launch_step(j.R, j.shape, cur, prev, out, last ? j.S : nullptr, j.mask,
+                                   j.B, j.H, j.W, a, last ? j.partials : nullptr, s);
+        if (e != hipSuccess) return hip_fail(e, "fsi step launch");
+    }
+    if (n == 1) {
+        hipError_t e = hipMemcpyAsync(j.S, j.X, sizeof(float) * (size_t)j.B * j.H * j.W,
+                                      hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "cycle copy");
+    }
+    hipError_t e = launch_reduce(j.partials, tiles_per_image(j.shape, j.H, j.W), j.B, j.sums, s);
+    if (e != hipSuccess) return hip_fail(e, "residual reduce launch");
+    return EED4_OK;
+}
+
+int capture_cycle(const CycleJob &j, hipGraphExec_t *exec)
+{
+    *exec = nullptr;
+    hipStream_t cs = capture_stream();
+    if (!cs) return hip_fail(hipErrorInvalidValue, "capture stream");
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "begin capture");
+    int rc = enqueue_cycle(j, cs);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);
+    if (rc != EED4_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+    return EED4_OK;
+}
+
+struct InpaintLayout {
+    size_t X, Y, partials, sums, hist, total;
+};
+
+InpaintLayout inpaint_layout(int op, int B, int H, int W, int M)
+{
+    InpaintLayout L{};
+    size_t N = (size_t)B * H * W;
+    int tiles = tiles_per_image(0, H, W) * B;
+    size_t o = 0;
+    L.X = o; o = align_up(o + sizeof(float) * N);
+    L.Y = o; o = align_up(o + sizeof(float) * N);
+    L.partials = o; o = align_up(o + sizeof(double) * 2 * (size_t)tiles);
+    L.sums = o; o = align_up(o + sizeof(double) * 2 * (size_t)B);
+    L.hist = o;
+    if (op == EED4_OP_INPAINT) o = align_up(o + sizeof(double) * 2 * (size_t)B * M);
+    L.total = o;
+    return L;
+}
+
+int check_ws(void *ws, size_t ws_bytes, size_t need)
+{
+    if (!ws || ((uintptr_t)ws & 255) != 0 || ws_bytes < need) return EED4_EWORKSPACE;
+    return EED4_OK;
+}
+
+}  // namespace eed4
+
+using namespace eed4;
+
+extern "C" {
+
+int eed4_radius(float sigma)
+{
+    if (!(sigma >= 0.0f) || !std::isfinite(sigma)) return -1;
+    if (sigma == 0.0f) return 0;
+    double r = std::ceil(3.0 * (double)sigma);
+    return r <= (double)kRMax ? (int)r : -1;
+}
+
+size_t eed4_workspace_size(int op, int B, int H, int W, const eed4_params *p)
+{
+    if (check_params(p, B, H, W) == EED4_EINVAL) return 0;
+    if (op == EED4_OP_INPAINT || op == EED4_OP_CYCLE)
+        return inpaint_layout(op, B, H, W, p->max_cycles).total;
+    if (op == EED4_OP_BACKWARD) return backward_workspace(B, H, W, p);
+    return 0;
+}
+
+int eed4_inpaint(float *u, const uint8_t *mask, const float *known, int B, int H, int W,
+                 const eed4_params *p, float *ckpt, void *ws, size_t ws_bytes, void *stream,
+                 eed4_stats *stats, double *hist)
+{
+    int rc = check_params(p, B, H, W);
+    if (rc != EED4_OK) return rc;
+    if (!u || !mask || !known) return EED4_EINVAL;
+    const int M = p->max_cycles, R = eed4_radius(p->sigma);
+    InpaintLayout L = inpaint_layout(EED4_OP_INPAINT, B, H, W, M);
+    if ((rc = check_ws(ws, ws_bytes, L.total)) != EED4_OK) return rc;
+    char *base = (char *)ws;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t N = (size_t)B * H * W;
+
+    CycleJob j;
+    j.S = u; j.X = (float *)(base + L.X); j.Y = (float *)(base + L.Y);
+    j.mask = mask; j.B = B; j.H = H; j.W = W; j.R = R; j.shape = 0; j.n = p->cycle_len;
+    j.sigma = p->sigma; j.tau = p->tau; j.lambda = p->lambda;
+    j.partials = (double *)(base + L.partials); j.sums = (double *)(base + L.sums);
+    double *hist_dev = (double *)(base + L.hist);
+
+    hipError_t e = launch_hold(u, mask, known, N, s);
+    if (e != hipSuccess) return hip_fail(e, "hold launch");
+
+    hipGraphExec_t exec = nullptr;
+    if (!(p->flags & EED4_NO_GRAPH)) {
+        if ((rc = capture_cycle(j, &exec)) != EED4_OK) return rc;
+    }
+    std::vector<double> host(2 * (size_t)B);
+    int m = 0;
+    double worst_abs = 0.0, worst_rel = 0.0;
+    bool diverged = false;
+    for (; m < M; ++m) {
+        if (ckpt) {
+            e = hipMemcpyAsync(ckpt + (size_t)m * N, u, sizeof(float) * N,
+                               hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) { rc = hip_fail(e, "checkpoint copy"); break; }
+        }
+        if (exec) {
+            e = hipGraphLaunch(exec, s);
+            if (e != hipSuccess) { rc = hip_fail(e, "graph launch"); break; }
+        } else if ((rc = enqueue_cycle(j, s)) != EED4_OK) {
+            break;
+        }
+        if (hist) {
+            e = hipMemcpyAsync(hist_dev + 2 * (size_t)B * m, j.sums, sizeof(double) * 2 * B,
+                               hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) { rc = hip_fail(e, "history copy"); break; }
+        }
+        const bool need_host = p->tol > 0.0f || m == M - 1;
+        if (!need_host) continue;
+        e = hipMemcpyAsync(host.data(), j.sums, sizeof(double) * 2 * B, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { rc = hip_fail(e, "residual read-back"); break; }
+        worst_abs = worst_rel = 0.0;
+        for (int b = 0; b < B; ++b) {
+            double r = std::sqrt(host[2 * b]), nn = std::sqrt(host[2 * b + 1]);
+            if (!std::isfinite(r) || !std::isfinite(nn)) diverged = true;
+            double rel = nn > 0.0 ? r / nn : r;
+            worst_abs = std::fmax(worst_abs, r);
+            worst_rel = std::fmax(worst_rel, rel);
+        }
+        if (diverged) { ++m; break; }
+        const double crit = (p->flags & EED4_ABS_TOL) ? worst_abs : worst_rel;
+        if (p->tol > 0.0f && crit < (double)p->tol) { ++m; break; }
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (rc != EED4_OK) return rc;
+    if (m > M) m = M;
+    if (hist) {
+        std::vector<double> hd(2 * (size_t)B * m);
+        e = hipMemcpyAsync(hd.data(), hist_dev, sizeof(double) * hd.size(), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "history read-back");
+        for (size_t i = 0; i < hd.size(); ++i) hist[i] = std::sqrt(hd[i]);
+    }
+    if (stats) {
+        stats->cycles = m;
+        stats->residual = worst_abs;
+        stats->rel_residual = worst_rel;
+    }
+    return diverged ? EED4_EDIVERGED : EED4_OK;
+}
+
+int eed4_fsi_cycle(float *u, const uint8_t *mask, const float *known, int B, int H, int W,
+                   const eed4_params *p, void *ws, size_t ws_bytes, void *stream, double *d_sums)
+{
+    int rc = check_params(p, B, H, W);
+    if (rc != EED4_OK) return rc;
+    if (!u || !mask || !known || !d_sums) return EED4_EINVAL;
+    InpaintLayout L = inpaint_layout(EED4_OP_CYCLE, B, H, W, 1);
+    if ((rc = check_ws(ws, ws_bytes, L.total)) != EED4_OK) return rc;
+    char *base = (char *)ws;
+    hipStream_t s = (hipStream_t)stream;
+    CycleJob j;
+    j.S = u; j.X = (float *)(base + L.X); j.Y = (float *)(base + L.Y);
+    j.mask = mask; j.B = B; j.H = H; j.W = W; j.R = eed4_radius(p->sigma); j.shape = 0;
+    j.n = p->cycle_len; j.sigma = p->sigma; j.tau = p->tau; j.lambda = p->lambda;
+    j.partials = (double *)(base + L.partials); j.sums = d_sums;
+    hipError_t e = launch_hold(u, mask, known, (size_t)B * H * W, s);
+    if (e != hipSuccess) return hip_fail(e, "hold launch");
+    return enqueue_cycle(j, s);
+}
+
+int eed4_fsi_step(const float *ucur, const float *uprev, float *uout, const uint8_t *mask,
+                  int B, int H, int W, const eed4_params *p, int k, void *stream)
+{
+    int rc = check_params(p, B, H, W);
+    if (rc != EED4_OK) return rc;
+    if (!ucur || !uprev || !uout || !mask || k < 0) return EED4_EINVAL;
+    const size_t bytes = sizeof(float) * (size_t)B * H * W;
+    const char *c0 = (const char *)ucur, *o0 = (const char *)uout;
+    if (o0 < c0 + bytes && c0 < o0 + bytes) return EED4_EINVAL;
+    const int R = eed4_radius(p->sigma);
+    StepArgs a = make_args(p->sigma, R, p->tau, p->lambda, k);
+    hipError_t e = launch_step(R, 0, ucur, uprev, uout, nullptr, mask, B, H, W, a, nullptr,
+                               (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "fsi step launch");
+    return EED4_OK;
+}
+
+const char *eed4_strerror(int code)
+{
+    switch (code) {
+    case EED4_OK: return "success";
+    case EED4_EINVAL: return "invalid argument (size, pointer or parameter)";
+    case EED4_EUNSTABLE: return "time step outside (0, 1/16] (set EED4_ALLOW_LARGE_TAU to force)";
+    case EED4_EWORKSPACE: return "workspace missing, not 256-byte aligned or too small";
+    case EED4_EHIP: {
+        static thread_local std::string msg;
+        msg = "HIP error: " + g_last_hip;
+        return msg.c_str();
+    }
+    case EED4_EDIVERGED: return "non-finite cycle residual (diverged)";
+    default: return "unknown error code";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,128 @@
+// Forward kernels: Dirichlet hold, fused FSI inner step over a grid of
+// tiles (one workgroup per tile, batch of equal-size images), and the
+// deterministic FP64 reduction of the per-tile cycle residuals.
+#include "eed4_internal.h"
+#include "eed4_tile.h"
+
+namespace eed4 {
+
+// u = f on the known set K (eq. inpaintingModel).
+__global__ __launch_bounds__(256) void hold_kernel(float *u, const uint8_t *__restrict__ mask,
+                                                   const float *__restrict__ known, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        if (mask[i]) u[i] = known[i];
+}
+
+template <int R, int TW, int TH>
+__global__ __launch_bounds__(256) void step_kernel(const float *ucur, const float *uprev,
+                                                   float *uout, const float *ref,
+                                                   const uint8_t *__restrict__ mask, int H, int W,
+                                                   int nbx, int tiles_per_img, StepArgs a,
+                                                   double *partials)
+{
+    __shared__ __attribute__((aligned(16))) float smem[TileGeo<R, TW, TH>::SMEM];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int b = tile / tiles_per_img;
+    const int t = tile - b * tiles_per_img;
+    const int ty = t / nbx, tx = t - ty * nbx;
+    const size_t off = (size_t)b * H * W;
+    step_tile<R, TW, TH>(smem, ucur + off, uprev + off, uout + off, ref ? ref + off : nullptr,
+                         mask + off, H, W, ty, tx, a.w, a.tau, a.alpha, a.inv_lam2,
+                         partials ? partials + 2 * (size_t)tile : nullptr);
+}
+
+// sums[b] = fixed-order sum of the residual partials of image b's tiles.
+__global__ __launch_bounds__(256) void reduce_kernel(const double *partials, int tiles_per_img,
+                                                     double *sums)
+{
+    __shared__ double sd[256], sn[256];
+    const int b = blockIdx.x;
+    const double *p = partials + 2 * (size_t)b * tiles_per_img;
+    double d = 0.0, n = 0.0;
+    for (int i = threadIdx.x; i < tiles_per_img; i += 256) {
+        d += p[2 * i];
+        n += p[2 * i + 1];
+    }
+    sd[threadIdx.x] = d;
+    sn[threadIdx.x] = n;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            sd[threadIdx.x] += sd[threadIdx.x + s];
+            sn[threadIdx.x] += sn[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        sums[2 * b] = sd[0];
+        sums[2 * b + 1] = sn[0];
+    }
+}
+
+hipError_t launch_hold(float *u, const uint8_t *mask, const float *known, size_t n,
+                       hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(hold_kernel, dim3((unsigned)blocks), dim3(256), 0, s, u, mask, known, n);
+    return hipGetLastError();
+}
+
+int tiles_per_image(int shape, int H, int W)
+{
+    const TileShape ts = kTileShapes[shape];
+    return ((W + ts.tw - 1) / ts.tw) * ((H + ts.th - 1) / ts.th);
+}
+
+template <int R, int TW, int TH>
+static hipError_t launch_step_t(const float *ucur, const float *uprev, float *uout,
+                                const float *ref, const uint8_t *mask, int B, int H, int W,
+                                const StepArgs &a, double *partials, hipStream_t s)
+{
+    const int nbx = (W + TW - 1) / TW, nby = (H + TH - 1) / TH;
+    const int tpi = nbx * nby;
+    const long long ntiles = (long long)tpi * B;
+    if (ntiles <= 0 || ntiles > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((step_kernel<R, TW, TH>), dim3((unsigned)ntiles), dim3(256), 0, s, ucur,
+                       uprev, uout, ref, mask, H, W, nbx, tpi, a, partials);
+    return hipGetLastError();
+}
+
+template <int R>
+static hipError_t launch_step_r(int shape, const float *ucur, const float *uprev, float *uout,
+                                const float *ref, const uint8_t *mask, int B, int H, int W,
+                                const StepArgs &a, double *partials, hipStream_t s)
+{
+    switch (shape) {
+    case 0: return launch_step_t<R, 64, 32>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
+    case 1: return launch_step_t<R, 64, 16>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
+    case 2: return launch_step_t<R, 32, 32>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_step(int R, int shape, const float *ucur, const float *uprev, float *uout,
+                       const float *ref, const uint8_t *mask, int B, int H, int W,
+                       const StepArgs &a, double *partials, hipStream_t s)
+{
+    switch (R) {
+#define EED4_CASE(r) \
+    case r: return launch_step_r<r>(shape, ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
+        EED4_CASE(0) EED4_CASE(1) EED4_CASE(2) EED4_CASE(3) EED4_CASE(4)
+        EED4_CASE(5) EED4_CASE(6) EED4_CASE(7) EED4_CASE(8)
+#undef EED4_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_reduce(const double *partials, int tiles_per_img, int B, double *sums,
+                         hipStream_t s)
+{
+    hipLaunchKernelGGL(reduce_kernel, dim3(B), dim3(256), 0, s, partials, tiles_per_img, sums);
+    return hipGetLastError();
+}
+
+}  // namespace eed4

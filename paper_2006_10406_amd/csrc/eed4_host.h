@@ -1,0 +1,34 @@
+// Host-side helpers shared by the translation units of libeed4.
+#pragma once
+
+#include "eed4.h"
+#include "eed4_internal.h"
+
+#include <string>
+
+namespace eed4 {
+
+// One FSI cycle over a batch of B equal-size images.
+struct CycleJob {
+    float *S, *X, *Y;          // S: caller's u; X, Y: rotation buffers
+    const uint8_t *mask;
+    int B, H, W, R, shape, n;
+    float sigma, tau, lambda;
+    double *partials;          // per-tile residual partials
+    double *sums;              // [B][2] residual sums
+};
+
+extern thread_local std::string g_last_hip;
+int hip_fail(hipError_t e, const char *where);
+size_t align_up(size_t x);
+int check_params(const eed4_params *p, int B, int H, int W);
+int check_ws(void *ws, size_t ws_bytes, size_t need);
+StepArgs make_args(float sigma, int R, float tau, float lambda, int k);
+hipStream_t capture_stream();
+void cycle_roles(int k, int n, float *S, float *X, float *Y, float **cur, float **prev,
+                 float **out);
+int enqueue_cycle(const CycleJob &j, hipStream_t s);
+int capture_cycle(const CycleJob &j, hipGraphExec_t *exec);
+size_t backward_workspace(int B, int H, int W, const eed4_params *p);
+
+}  // namespace eed4

@@ -1,0 +1,85 @@
+// Internal declarations shared by the HIP translation units of libeed4.
+// Not part of the public ABI (include/eed4.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace eed4 {
+
+constexpr int kRMax = 8;        // largest Gaussian radius (sigma <= 8/3)
+constexpr int kThreads = 256;   // threads per workgroup of the tile kernels
+
+// Per-launch constants of one inner FSI step.
+struct StepArgs {
+    float w[2 * kRMax + 1];  // sampled Gaussian, w[j + R], j = -R..R, sums to 1
+    float tau;               // time step
+    float alpha;             // FSI weight alpha_k = (4k+2)/(2k+3)
+    float inv_lam2;          // 1 / lambda^2
+};
+
+// Output tile of the fused step kernels.
+struct TileShape {
+    int tw, th;
+};
+
+// Tile shapes compiled into the library (index = config id).
+constexpr int kNumTileShapes = 3;
+constexpr TileShape kTileShapes[kNumTileShapes] = {{64, 32}, {64, 16}, {32, 32}};
+
+// Device-side descriptor of one image of an uneven batch.
+struct ImageDesc {
+    float *S;              // caller's u: cycle-start state and result
+    float *X, *Y;          // two workspace rotation buffers
+    const uint8_t *mask;
+    const float *known;
+    int H, W;
+    int nbx;               // tiles per row
+    int tile0;             // first tile of this image in the full tile list
+    float inv_lam2;
+    int pad;
+};
+
+// One queue entry of the batched persistent kernel.
+struct TileRef {
+    int img, ty, tx, slot;  // slot: index of the residual partial of this tile
+};
+
+// ---- launchers (eed4_forward.hip) ----
+hipError_t launch_hold(float *u, const uint8_t *mask, const float *known, size_t n,
+                       hipStream_t s);
+hipError_t launch_step(int R, int shape, const float *ucur, const float *uprev, float *uout,
+                       const float *ref, const uint8_t *mask, int B, int H, int W,
+                       const StepArgs &a, double *partials, hipStream_t s);
+hipError_t launch_reduce(const double *partials, int tiles_per_img, int B, double *sums,
+                         hipStream_t s);
+int tiles_per_image(int shape, int H, int W);
+
+// ---- launchers (eed4_batched.hip) ----
+hipError_t launch_batched_step(int R, int shape, int grid, const ImageDesc *imgs,
+                               const TileRef *queue, const int *qlen, unsigned *counter,
+                               int sel_cur, int sel_prev, int sel_out, int residual,
+                               const StepArgs &a, double *partials, hipStream_t s);
+hipError_t launch_reset_counter(unsigned *counter, hipStream_t s);
+hipError_t launch_batched_reduce(const ImageDesc *imgs, const double *partials,
+                                 const int *tiles_img, int B, double *sums, hipStream_t s);
+int batched_occupancy_grid(int R, int shape);
+
+// ---- launchers (eed4_adjoint.hip) ----
+hipError_t launch_adjoint_a(int R, const float *u, const float *abar_next, const uint8_t *mask,
+                            int B, int H, int W, const StepArgs &a, float *qx, float *qy,
+                            float *pr, double *lam_partials, hipStream_t s);
+hipError_t launch_adjoint_b(int R, const float *qx, const float *qy, const float *pr,
+                            float *abar_next, float *abar_cur, const uint8_t *mask,
+                            float *grad_known, int B, int H, int W, const StepArgs &a,
+                            int first_step, hipStream_t s);
+hipError_t launch_adjoint_final(const float *abar0, const uint8_t *mask, float *grad_known,
+                                float *grad_init, size_t n, hipStream_t s);
+hipError_t launch_lambda_reduce(const double *lam_partials, int tiles_per_img, int B,
+                                double *acc, hipStream_t s);
+hipError_t launch_lambda_store(const double *acc, float *grad_lambda, int B, hipStream_t s);
+hipError_t launch_fill_double(double *p, size_t n, hipStream_t s);
+int adjoint_tiles_per_image(int H, int W);
+
+}  // namespace eed4

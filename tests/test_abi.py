@@ -1,0 +1,92 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol
+include/eed4.h declares, and rejects bad arguments before any GPU work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "eed4.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(eed4_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2006_10406_amd import _lib
+    return _lib.lib()
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ("eed4_inpaint", "eed4_fsi_cycle", "eed4_backward", "eed4_inpaint_batched",
+              "eed4_workspace_size", "eed4_strerror", "eed4_radius"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2006_10406_amd import _lib
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+        assert n in _lib.EXPORTED
+
+
+def test_radius(lib):
+    assert lib.eed4_radius(0.0) == 0
+    assert lib.eed4_radius(1.0) == 3
+    assert lib.eed4_radius(1.5) == 5
+    assert lib.eed4_radius(2.0) == 6
+    assert lib.eed4_radius(2.66) == 8
+    assert lib.eed4_radius(2.7) == -1
+    assert lib.eed4_radius(-0.5) == -1
+    assert lib.eed4_radius(float("nan")) == -1
+
+
+def test_workspace_size(lib):
+    import paper_2006_10406_amd as e
+    p = e.params(0.05, 1.0, 0.05, 10, 20)
+    n1 = e.eed4_workspace_size(e.EED4_OP_INPAINT, 1, 64, 64, p)
+    assert n1 >= 2 * 64 * 64 * 4
+    assert e.eed4_workspace_size(e.EED4_OP_INPAINT, 2, 64, 64, p) > n1
+    assert e.eed4_workspace_size(e.EED4_OP_CYCLE, 1, 64, 64, p) >= 2 * 64 * 64 * 4
+    assert e.eed4_workspace_size(e.EED4_OP_INPAINT, 0, 64, 64, p) == 0
+    bad = e.params(-1.0, 1.0, 0.05, 10, 20)
+    assert e.eed4_workspace_size(e.EED4_OP_INPAINT, 1, 64, 64, bad) == 0
+    assert e.eed4_workspace_size(99, 1, 64, 64, p) == 0
+
+
+def _call_inpaint(lib, p, ws=0x1000, wsz=1 << 40, B=1, H=8, W=8, ptr=0x2000):
+    from paper_2006_10406_amd import _lib
+    st = _lib.eed4_stats()
+    return lib.eed4_inpaint(ptr, ptr, ptr, B, H, W, ctypes.byref(p), None, ws, wsz, None,
+                            ctypes.byref(st), None)
+
+
+def test_argument_errors_before_any_gpu_work(lib):
+    import paper_2006_10406_amd as e
+    ok = e.params(0.05, 1.0, 0.05, 10, 2)
+    assert _call_inpaint(lib, e.params(0.05, 1.0, 0.07, 10, 2)) == e._lib.EED4_EUNSTABLE
+    assert _call_inpaint(lib, e.params(0.0, 1.0, 0.05, 10, 2)) == e._lib.EED4_EINVAL
+    assert _call_inpaint(lib, e.params(0.05, 3.0, 0.05, 10, 2)) == e._lib.EED4_EINVAL
+    assert _call_inpaint(lib, e.params(0.05, 1.0, 0.05, 0, 2)) == e._lib.EED4_EINVAL
+    assert _call_inpaint(lib, e.params(0.05, 1.0, 0.05, 10, 0)) == e._lib.EED4_EINVAL
+    assert _call_inpaint(lib, e.params(0.05, 1.0, -0.01, 10, 2)) == e._lib.EED4_EINVAL
+    assert _call_inpaint(lib, e.params(0.05, 1.0, 0.05, 10, 2, tol=-1.0)) == e._lib.EED4_EINVAL
+    assert _call_inpaint(lib, ok, H=0) == e._lib.EED4_EINVAL
+    assert _call_inpaint(lib, ok, ptr=0) == e._lib.EED4_EINVAL
+    assert _call_inpaint(lib, ok, ws=0) == e._lib.EED4_EWORKSPACE
+    assert _call_inpaint(lib, ok, ws=0x1001) == e._lib.EED4_EWORKSPACE
+    assert _call_inpaint(lib, ok, wsz=16) == e._lib.EED4_EWORKSPACE
+    big = e.params(0.05, 1.0, 0.07, 10, 2, flags=e.EED4_ALLOW_LARGE_TAU)
+    assert _call_inpaint(lib, big, ws=0) == e._lib.EED4_EWORKSPACE
+
+
+def test_strerror(lib):
+    import paper_2006_10406_amd as e
+    for c in (0, -1, -2, -3, -4, -5, 7):
+        assert isinstance(e.eed4_strerror(c), str) and e.eed4_strerror(c)

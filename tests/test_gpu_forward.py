@@ -1,0 +1,178 @@
+"""Parity of the fused HIP forward path (eed4_fsi_cycle, eed4_inpaint) with
+the FP64 oracle, through the C ABI.
+
+Bar: relative L2 <= 1e-5 for one FSI cycle started from the same FP32 state,
+RMSE <= 1e-4 for multi-cycle runs at equal cycle counts; the FP32-vs-FP64
+error of every case is printed.  Inputs come from the seeded generator.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth import WORKLOADS, make_batch, make_problem
+from tests.helpers import REL_L2_PER_CYCLE, RMSE_STEADY, announce, rel_l2, rmse, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+import paper_2006_10406_amd as eed4  # noqa: E402
+
+
+def gpu_cycle(states, mask, known, lam, sigma, tau, n):
+    """One eed4_fsi_cycle over a batch of FP32 start states; returns (u, sums)."""
+    u = to_dev(states.astype(np.float32))
+    sums = torch.zeros((states.shape[0], 2), dtype=torch.float64, device="cuda")
+    p = eed4.params(lam, sigma, tau, n, 1)
+    eed4.eed4_fsi_cycle(u, to_dev(mask), to_dev(known.astype(np.float32)), p, sums)
+    torch.cuda.synchronize()
+    return u.cpu().numpy(), sums.cpu().numpy()
+
+
+def oracle_cycle(states, mask, known, lam, sigma, tau, n):
+    u, _, hist = oracle.inpaint(states.astype(np.float32).astype(np.float64), mask,
+                                known.astype(np.float32), lam, sigma, tau, n, 1)
+    return u, hist
+
+
+def test_small64_per_cycle_parity():
+    wl = WORKLOADS["small64"]
+    announce(f"small64 per-cycle parity, {wl.M} cycles of {wl.n}")
+    pr = make_problem(wl.H, wl.W, wl.n_ellipses, wl.ramp, wl.noise_std, wl.density, wl.seed_base)
+    _, cyc, hist, ck = oracle.inpaint(pr["u_init"], pr["mask"], pr["known"], wl.lam, wl.sigma,
+                                      wl.tau, wl.n, wl.M, checkpoints=True)
+    M = ck.shape[0]
+    masks = np.repeat(pr["mask"][None], M, 0)
+    knowns = np.repeat(pr["known"][None], M, 0)
+    got, sums = gpu_cycle(ck, masks, knowns, wl.lam, wl.sigma, wl.tau, wl.n)
+    ref, rh = oracle_cycle(ck, masks, knowns, wl.lam, wl.sigma, wl.tau, wl.n)
+    errs = [rel_l2(got[m], ref[m]) for m in range(M)]
+    print(f"small64 per-cycle rel L2: max {max(errs):.3e} mean {np.mean(errs):.3e}")
+    assert max(errs) <= REL_L2_PER_CYCLE
+    # FP64 residual sums against the oracle's cycle residuals
+    assert np.allclose(np.sqrt(sums[:, 1]), rh[0, :, 1], rtol=1e-6)
+    r_gpu = np.sqrt(sums[:, 0])
+    assert np.allclose(r_gpu, rh[0, :, 0], rtol=1e-2, atol=1e-6)
+
+
+def test_small64_full_run():
+    wl = WORKLOADS["small64"]
+    announce("small64 full run, eed4_inpaint vs oracle")
+    pr = make_problem(wl.H, wl.W, wl.n_ellipses, wl.ramp, wl.noise_std, wl.density, wl.seed_base)
+    ref, cyc, rh = oracle.inpaint(pr["u_init"], pr["mask"], pr["known"], wl.lam, wl.sigma,
+                                  wl.tau, wl.n, wl.M)
+    u = to_dev(pr["u_init"])
+    st, hist = eed4.eed4_inpaint(u, to_dev(pr["mask"]), to_dev(pr["known"]),
+                                 eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, wl.M), history=True)
+    got = u.cpu().numpy()
+    e = rmse(got, ref)
+    print(f"small64 after {st.cycles} cycles: RMSE vs FP64 {e:.3e}, rel L2 {rel_l2(got, ref):.3e}; "
+          f"RMSE vs ground truth {rmse(got, pr['image']):.4f} (oracle {rmse(ref, pr['image']):.4f})")
+    assert st.cycles == wl.M
+    assert e <= RMSE_STEADY
+    assert np.array_equal(got[pr["mask"] != 0], pr["known"][pr["mask"] != 0])
+    assert np.allclose(hist[:, 0, 1], rh[:, 1], rtol=1e-5)
+
+
+@pytest.mark.parametrize("H,W,sigma,lam", [
+    (37, 53, 1.0, 0.05), (1, 1, 1.0, 0.1), (1, 100, 1.5, 0.05), (100, 1, 1.5, 0.05),
+    (3, 5, 2.0, 0.03), (65, 33, 0.0, 0.1), (70, 130, 0.5, 0.02), (97, 67, 2.6, 0.05),
+    (64, 64, 1.5, 0.03), (33, 129, 2.0, 0.02)])
+def test_ragged_shapes_and_radii(H, W, sigma, lam):
+    announce(f"ragged {H}x{W} sigma={sigma}")
+    pr = make_problem(H, W, 3, True, 0.01, 0.1, 77 + H * 1000 + W)
+    n, tau = 7, 0.05
+    # two cycles: the second starts from a non-trivial state
+    _, _, _, ck = oracle.inpaint(pr["u_init"], pr["mask"], pr["known"], lam, sigma, tau, n, 2,
+                                 checkpoints=True)
+    masks = np.repeat(pr["mask"][None], 2, 0)
+    knowns = np.repeat(pr["known"][None], 2, 0)
+    got, _ = gpu_cycle(ck, masks, knowns, lam, sigma, tau, n)
+    ref, _ = oracle_cycle(ck, masks, knowns, lam, sigma, tau, n)
+    errs = [rel_l2(got[m], ref[m]) for m in range(2)]
+    print(f"{H}x{W} sigma {sigma}: rel L2 {max(errs):.3e}")
+    assert max(errs) <= REL_L2_PER_CYCLE
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_short_cycles(n):
+    announce(f"short cycle n={n}")
+    pr = make_problem(40, 45, 4, True, 0.01, 0.08, 99 + n)
+    st = pr["u_init"][None]
+    got, _ = gpu_cycle(st, pr["mask"][None], pr["known"][None], 0.05, 1.0, 0.05, n)
+    ref, _ = oracle_cycle(st, pr["mask"][None], pr["known"][None], 0.05, 1.0, 0.05, n)
+    assert rel_l2(got, ref) <= REL_L2_PER_CYCLE
+
+
+def test_constant_image_is_stationary_bitwise():
+    announce("constant image")
+    H, W, c = 70, 90, np.float32(0.3721)
+    u0 = np.full((H, W), c, np.float32)
+    mask = np.zeros((H, W), np.uint8)
+    mask[5, 7] = 1
+    u = to_dev(u0)
+    eed4.eed4_inpaint(u, to_dev(mask), to_dev(u0), eed4.params(0.05, 2.0, 0.05, 10, 3))
+    assert np.array_equal(u.cpu().numpy(), u0)
+
+
+def test_deterministic_and_graph_equivalent():
+    announce("determinism, graph vs direct launches")
+    pr = make_problem(200, 150, 10, True, 0.01, 0.05, 4242)
+    outs = []
+    for flags in (0, 0, eed4.EED4_NO_GRAPH):
+        u = to_dev(pr["u_init"])
+        eed4.eed4_inpaint(u, to_dev(pr["mask"]), to_dev(pr["known"]),
+                          eed4.params(0.03, 1.5, 0.05, 15, 4, flags=flags))
+        outs.append(u.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[2])
+
+
+def test_equal_size_batch_matches_single_images():
+    announce("equal-size batch vs single images")
+    wl = WORKLOADS["adjoint16"]
+    b = make_batch(wl, B=3, shape=(96, 80))
+    p = eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, 3)
+    u = to_dev(b["u_init"])
+    eed4.eed4_inpaint(u, to_dev(b["mask"]), to_dev(b["known"]), p)
+    batch = u.cpu().numpy()
+    for i in range(3):
+        ui = to_dev(b["u_init"][i])
+        eed4.eed4_inpaint(ui, to_dev(b["mask"][i]), to_dev(b["known"][i]), p)
+        assert np.array_equal(ui.cpu().numpy(), batch[i])
+
+
+def test_stop_rule_and_steady_state_512():
+    wl = WORKLOADS["single512"]
+    announce("single512 to relative residual 1e-4, then oracle at equal cycle count")
+    pr = make_problem(wl.H, wl.W, wl.n_ellipses, wl.ramp, wl.noise_std, wl.density, wl.seed_base)
+    u = to_dev(pr["u_init"])
+    st, hist = eed4.eed4_inpaint(u, to_dev(pr["mask"]), to_dev(pr["known"]),
+                                 eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, wl.M, tol=wl.tol),
+                                 history=True)
+    got = u.cpu().numpy()
+    rel = hist[:, 0, 0] / hist[:, 0, 1]
+    print(f"single512: {st.cycles} cycles, final relative residual {st.rel_residual:.3e}")
+    assert st.cycles < wl.M and st.rel_residual < wl.tol
+    assert rel[-1] < wl.tol and np.all(rel[:-1] >= wl.tol)
+    ref, cyc, _ = oracle.inpaint(pr["u_init"], pr["mask"], pr["known"], wl.lam, wl.sigma,
+                                 wl.tau, wl.n, st.cycles)
+    e = rmse(got, ref)
+    print(f"single512 RMSE vs FP64 at {st.cycles} cycles: {e:.3e} (rel L2 {rel_l2(got, ref):.3e}); "
+          f"RMSE vs ground truth {rmse(got, pr['image']):.4f}")
+    assert e <= RMSE_STEADY
+
+
+def test_large4096_first_cycle_parity():
+    wl = WORKLOADS["large4096"]
+    announce("large4096 first cycle (bench launch configuration) vs oracle")
+    pr = make_problem(wl.H, wl.W, wl.n_ellipses, wl.ramp, wl.noise_std, wl.density, wl.seed_base)
+    u0 = np.where(pr["mask"] != 0, pr["known"], pr["u_init"]).astype(np.float32)
+    got, sums = gpu_cycle(u0[None], pr["mask"][None], pr["known"][None], wl.lam, wl.sigma,
+                          wl.tau, wl.n)
+    ref, rh = oracle_cycle(u0[None], pr["mask"][None], pr["known"][None], wl.lam, wl.sigma,
+                           wl.tau, wl.n)
+    e = rel_l2(got[0], ref[0])
+    print(f"large4096 first cycle rel L2 {e:.3e}, max abs {np.abs(got[0] - ref[0]).max():.3e}")
+    assert e <= REL_L2_PER_CYCLE
