@@ -120,6 +120,24 @@ def adjoint_ratio(eed4, torch, args):
             "workload": f"adjoint16: {B} x {H}x{W}, {wl.M} cycles of {wl.n}, checkpoint per cycle"}
 
 
+def probe(eed4, torch, u_init, mask, wl):
+    """Launch the fused step 3 x n times, then copy 64 MiB device to device."""
+    a, b, c = u_init.clone(), u_init.clone(), u_init.clone()
+    ps = eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, 1)
+    roles = lambda k: (a, a, b) if k == 0 else ((b, a, c) if k == 1 else
+                                                 ((b, c, c) if k % 2 else (c, b, b)))
+    for _ in range(3):
+        for k in range(wl.n):
+            cur, prev, out = roles(k)
+            eed4.eed4_fsi_step(cur, prev, out, mask, ps, k)
+    torch.cuda.synchronize()
+    src = torch.ones(16 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"probe done: {3 * wl.n} step launches, one copy of {src.numel() * 4} bytes")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,6 +147,9 @@ def main():
                     help="cycles of back-to-back eed4_fsi_step launches for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--probe", action="store_true",
+                    help="counter probe: 3 cycles of fused step launches on the workload, then "
+                         "a plain 64 MiB device copy (calibrates FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -155,6 +176,10 @@ def main():
     ws = torch.empty(eed4.eed4_workspace_size(eed4.EED4_OP_INPAINT, 1, H, W, pt) + 256,
                      dtype=torch.uint8, device=dev)
     wsv = ws[(-ws.data_ptr()) % 256:]
+
+    if args.probe:
+        probe(eed4, torch, u_init, mask, wl)
+        return
 
     # ---- whole-path timing: warmup cycles, then exactly K timed cycles ----
     u = u_init.clone()

@@ -65,6 +65,10 @@ extern "C" {
 /* Launch each inner step directly instead of replaying a captured hipGraph
  * of the cycle (same results; for comparison). */
 #define EED4_NO_GRAPH        0x4
+/* Use the workgroup-tile step kernel (64 x 32 outputs per 256-thread
+ * workgroup, stages separated by barriers) instead of the default wave-strip
+ * kernel.  Both compute the same step; results agree to rounding. */
+#define EED4_TILE_KERNEL     0x8
 
 /* ---- workspace sizing (eed4_workspace_size op) ---- */
 #define EED4_OP_INPAINT  1

@@ -22,6 +22,7 @@ import torch
 
 from . import _lib
 from ._lib import (EED4_ABS_TOL, EED4_ALLOW_LARGE_TAU, EED4_NO_GRAPH, EED4_OP_BACKWARD,
+                   EED4_TILE_KERNEL,
                    EED4_OP_CYCLE, EED4_OP_INPAINT, eed4_image, eed4_params, eed4_stats)
 
 _lib.lib()  # fail loudly at import if libeed4.so is missing
@@ -29,7 +30,7 @@ _lib.lib()  # fail loudly at import if libeed4.so is missing
 __all__ = [
     "EED4Error", "params", "eed4_radius", "eed4_workspace_size", "eed4_inpaint",
     "eed4_fsi_cycle", "eed4_fsi_step", "eed4_backward", "eed4_batched_workspace_size", "eed4_inpaint_batched",
-    "eed4_strerror", "EED4_ABS_TOL", "EED4_ALLOW_LARGE_TAU", "EED4_NO_GRAPH",
+    "eed4_strerror", "EED4_ABS_TOL", "EED4_ALLOW_LARGE_TAU", "EED4_NO_GRAPH", "EED4_TILE_KERNEL",
     "EED4_OP_INPAINT", "EED4_OP_CYCLE", "EED4_OP_BACKWARD", "library_path",
 ]
 

@@ -18,6 +18,7 @@ EED4_EDIVERGED = -5
 EED4_ALLOW_LARGE_TAU = 0x1
 EED4_ABS_TOL = 0x2
 EED4_NO_GRAPH = 0x4
+EED4_TILE_KERNEL = 0x8
 
 EED4_OP_INPAINT = 1
 EED4_OP_CYCLE = 2

@@ -109,7 +109,7 @@ int enqueue_cycle(const CycleJob &j, hipStream_t s)
                                       hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return hip_fail(e, "cycle copy");
     }
-    hipError_t e = launch_reduce(j.partials, tiles_per_image(j.shape, j.H, j.W), j.B, j.sums, s);
+    hipError_t e = launch_reduce(j.partials, tiles_per_image(j.shape, j.R, j.H, j.W), j.B, j.sums, s);
     if (e != hipSuccess) return hip_fail(e, "residual reduce launch");
     return EED4_OK;
 }
@@ -139,20 +139,37 @@ struct InpaintLayout {
     size_t X, Y, partials, sums, hist, total;
 };
 
-InpaintLayout inpaint_layout(int op, int B, int H, int W, int M)
+// residual partials: enough for the largest per-image count of any kernel shape
+int max_partials_per_image(int R, int H, int W)
+{
+    int m = 0;
+    for (int sh = 0; sh < kNumShapes; ++sh) {
+        int t = tiles_per_image(sh, R, H, W);
+        if (t > m) m = t;
+    }
+    return m;
+}
+
+InpaintLayout inpaint_layout(int op, int B, int H, int W, int R, int M)
 {
     InpaintLayout L{};
     size_t N = (size_t)B * H * W;
-    int tiles = tiles_per_image(0, H, W) * B;
+    size_t tiles = (size_t)max_partials_per_image(R, H, W) * B;
     size_t o = 0;
     L.X = o; o = align_up(o + sizeof(float) * N);
     L.Y = o; o = align_up(o + sizeof(float) * N);
-    L.partials = o; o = align_up(o + sizeof(double) * 2 * (size_t)tiles);
+    L.partials = o; o = align_up(o + sizeof(double) * 2 * tiles);
     L.sums = o; o = align_up(o + sizeof(double) * 2 * (size_t)B);
     L.hist = o;
     if (op == EED4_OP_INPAINT) o = align_up(o + sizeof(double) * 2 * (size_t)B * M);
     L.total = o;
     return L;
+}
+
+// Fused step kernel used by the single-image / equal-size-batch entry points.
+int step_shape(const eed4_params *p)
+{
+    return (p->flags & EED4_TILE_KERNEL) ? 0 : kShapeStrip;
 }
 
 int check_ws(void *ws, size_t ws_bytes, size_t need)
@@ -179,7 +196,7 @@ size_t eed4_workspace_size(int op, int B, int H, int W, const eed4_params *p)
 {
     if (check_params(p, B, H, W) == EED4_EINVAL) return 0;
     if (op == EED4_OP_INPAINT || op == EED4_OP_CYCLE)
-        return inpaint_layout(op, B, H, W, p->max_cycles).total;
+        return inpaint_layout(op, B, H, W, eed4_radius(p->sigma), p->max_cycles).total;
     if (op == EED4_OP_BACKWARD) return backward_workspace(B, H, W, p);
     return 0;
 }
@@ -192,7 +209,7 @@ int eed4_inpaint(float *u, const uint8_t *mask, const float *known, int B, int H
     if (rc != EED4_OK) return rc;
     if (!u || !mask || !known) return EED4_EINVAL;
     const int M = p->max_cycles, R = eed4_radius(p->sigma);
-    InpaintLayout L = inpaint_layout(EED4_OP_INPAINT, B, H, W, M);
+    InpaintLayout L = inpaint_layout(EED4_OP_INPAINT, B, H, W, R, M);
     if ((rc = check_ws(ws, ws_bytes, L.total)) != EED4_OK) return rc;
     char *base = (char *)ws;
     hipStream_t s = (hipStream_t)stream;
@@ -200,7 +217,7 @@ int eed4_inpaint(float *u, const uint8_t *mask, const float *known, int B, int H
 
     CycleJob j;
     j.S = u; j.X = (float *)(base + L.X); j.Y = (float *)(base + L.Y);
-    j.mask = mask; j.B = B; j.H = H; j.W = W; j.R = R; j.shape = 0; j.n = p->cycle_len;
+    j.mask = mask; j.B = B; j.H = H; j.W = W; j.R = R; j.shape = step_shape(p); j.n = p->cycle_len;
     j.sigma = p->sigma; j.tau = p->tau; j.lambda = p->lambda;
     j.partials = (double *)(base + L.partials); j.sums = (double *)(base + L.sums);
     double *hist_dev = (double *)(base + L.hist);
@@ -274,13 +291,13 @@ int eed4_fsi_cycle(float *u, const uint8_t *mask, const float *known, int B, int
     int rc = check_params(p, B, H, W);
     if (rc != EED4_OK) return rc;
     if (!u || !mask || !known || !d_sums) return EED4_EINVAL;
-    InpaintLayout L = inpaint_layout(EED4_OP_CYCLE, B, H, W, 1);
+    InpaintLayout L = inpaint_layout(EED4_OP_CYCLE, B, H, W, eed4_radius(p->sigma), 1);
     if ((rc = check_ws(ws, ws_bytes, L.total)) != EED4_OK) return rc;
     char *base = (char *)ws;
     hipStream_t s = (hipStream_t)stream;
     CycleJob j;
     j.S = u; j.X = (float *)(base + L.X); j.Y = (float *)(base + L.Y);
-    j.mask = mask; j.B = B; j.H = H; j.W = W; j.R = eed4_radius(p->sigma); j.shape = 0;
+    j.mask = mask; j.B = B; j.H = H; j.W = W; j.R = eed4_radius(p->sigma); j.shape = step_shape(p);
     j.n = p->cycle_len; j.sigma = p->sigma; j.tau = p->tau; j.lambda = p->lambda;
     j.partials = (double *)(base + L.partials); j.sums = d_sums;
     hipError_t e = launch_hold(u, mask, known, (size_t)B * H * W, s);
@@ -299,7 +316,7 @@ int eed4_fsi_step(const float *ucur, const float *uprev, float *uout, const uint
     if (o0 < c0 + bytes && c0 < o0 + bytes) return EED4_EINVAL;
     const int R = eed4_radius(p->sigma);
     StepArgs a = make_args(p->sigma, R, p->tau, p->lambda, k);
-    hipError_t e = launch_step(R, 0, ucur, uprev, uout, nullptr, mask, B, H, W, a, nullptr,
+    hipError_t e = launch_step(R, step_shape(p), ucur, uprev, uout, nullptr, mask, B, H, W, a, nullptr,
                                (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "fsi step launch");
     return EED4_OK;

@@ -3,6 +3,7 @@
 // deterministic FP64 reduction of the per-tile cycle residuals.
 #include "eed4_internal.h"
 #include "eed4_tile.h"
+#include "eed4_strip.h"
 
 namespace eed4 {
 
@@ -31,6 +32,39 @@ __global__ __launch_bounds__(256) void step_kernel(const float *ucur, const floa
     step_tile<R, TW, TH>(smem, ucur + off, uprev + off, uout + off, ref ? ref + off : nullptr,
                          mask + off, H, W, ty, tx, a.w, a.tau, a.alpha, a.inv_lam2,
                          partials ? partials + 2 * (size_t)tile : nullptr);
+}
+
+template <int R, bool RES>
+__global__ __launch_bounds__(256) void strip_kernel(const float *ucur, const float *uprev,
+                                                    float *uout, const float *ref,
+                                                    const uint8_t *__restrict__ mask, int H, int W,
+                                                    int nstrip, int per_img, int nitems, StepArgs a,
+                                                    double *partials)
+{
+    using G = StripGeo<R>;
+    __shared__ float lds[4 * G::LDS];
+    const int wave = threadIdx.x >> 6;
+    // wave-uniform: keep the work item (and all that derives from it) in SGPRs
+    const int item = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + wave);
+    if (item >= nitems) return;  // whole wave; the kernel has no workgroup barrier
+    const int b = item / per_img;
+    const int r = item - b * per_img;
+    const int seg = r / nstrip, strip = r - seg * nstrip;
+    const size_t off = (size_t)b * H * W;
+    StripArgs s;
+    s.ucur = ucur + off;
+    s.uprev = uprev + off;
+    s.uout = uout + off;
+    s.ref = RES ? ref + off : nullptr;
+    s.mask = mask + off;
+    s.H = H;
+    s.W = W;
+    s.X0 = strip * G::SW;
+    s.Y0 = seg * G::OH;
+    s.tau = a.tau;
+    s.alpha = a.alpha;
+    s.il2q = 0.25f * a.inv_lam2;
+    strip_step<R, RES>(lds + wave * G::LDS, s, a.w, RES ? partials + 2 * (size_t)item : nullptr);
 }
 
 // sums[b] = fixed-order sum of the residual partials of image b's tiles.
@@ -71,10 +105,46 @@ hipError_t launch_hold(float *u, const uint8_t *mask, const float *known, size_t
     return hipGetLastError();
 }
 
-int tiles_per_image(int shape, int H, int W)
+template <int R>
+static int strip_items(int H, int W)
 {
+    using G = StripGeo<R>;
+    return ((W + G::SW - 1) / G::SW) * ((H + G::OH - 1) / G::OH);
+}
+
+int tiles_per_image(int shape, int R, int H, int W)
+{
+    if (shape == kShapeStrip) {
+        switch (R) {
+#define EED4_CASE(r) case r: return strip_items<r>(H, W);
+            EED4_CASE(0) EED4_CASE(1) EED4_CASE(2) EED4_CASE(3) EED4_CASE(4)
+            EED4_CASE(5) EED4_CASE(6) EED4_CASE(7) EED4_CASE(8)
+#undef EED4_CASE
+        default: return 0;
+        }
+    }
     const TileShape ts = kTileShapes[shape];
     return ((W + ts.tw - 1) / ts.tw) * ((H + ts.th - 1) / ts.th);
+}
+
+template <int R>
+static hipError_t launch_strip_t(const float *ucur, const float *uprev, float *uout,
+                                 const float *ref, const uint8_t *mask, int B, int H, int W,
+                                 const StepArgs &a, double *partials, hipStream_t s)
+{
+    using G = StripGeo<R>;
+    const int nstrip = (W + G::SW - 1) / G::SW;
+    const int per_img = nstrip * ((H + G::OH - 1) / G::OH);
+    const long long nitems = (long long)per_img * B;
+    const long long nblk = (nitems + 3) / 4;
+    if (nitems <= 0 || nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (ref)
+        hipLaunchKernelGGL((strip_kernel<R, true>), dim3((unsigned)nblk), dim3(256), 0, s, ucur,
+                           uprev, uout, ref, mask, H, W, nstrip, per_img, (int)nitems, a, partials);
+    else
+        hipLaunchKernelGGL((strip_kernel<R, false>), dim3((unsigned)nblk), dim3(256), 0, s, ucur,
+                           uprev, uout, ref, mask, H, W, nstrip, per_img, (int)nitems, a, partials);
+    return hipGetLastError();
 }
 
 template <int R, int TW, int TH>
@@ -100,6 +170,7 @@ static hipError_t launch_step_r(int shape, const float *ucur, const float *uprev
     case 0: return launch_step_t<R, 64, 32>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
     case 1: return launch_step_t<R, 64, 16>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
     case 2: return launch_step_t<R, 32, 32>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
+    case kShapeStrip: return launch_strip_t<R>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
     default: return hipErrorInvalidValue;
     }
 }

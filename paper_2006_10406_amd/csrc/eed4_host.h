@@ -23,6 +23,7 @@ int hip_fail(hipError_t e, const char *where);
 size_t align_up(size_t x);
 int check_params(const eed4_params *p, int B, int H, int W);
 int check_ws(void *ws, size_t ws_bytes, size_t need);
+int step_shape(const eed4_params *p);
 StepArgs make_args(float sigma, int R, float tau, float lambda, int k);
 hipStream_t capture_stream();
 void cycle_roles(int k, int n, float *S, float *X, float *Y, float **cur, float **prev,

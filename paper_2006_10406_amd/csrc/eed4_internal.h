@@ -24,9 +24,13 @@ struct TileShape {
     int tw, th;
 };
 
-// Tile shapes compiled into the library (index = config id).
+// Kernel shapes compiled into the library (index = config id): 0..2 are
+// workgroup tiles (tw x th outputs per 256-thread workgroup); 3 is the
+// wave-strip kernel (60 columns x a radius-dependent row count per wave).
 constexpr int kNumTileShapes = 3;
 constexpr TileShape kTileShapes[kNumTileShapes] = {{64, 32}, {64, 16}, {32, 32}};
+constexpr int kShapeStrip = 3;
+constexpr int kNumShapes = 4;
 
 // Device-side descriptor of one image of an uneven batch.
 struct ImageDesc {
@@ -54,7 +58,7 @@ hipError_t launch_step(int R, int shape, const float *ucur, const float *uprev, 
                        const StepArgs &a, double *partials, hipStream_t s);
 hipError_t launch_reduce(const double *partials, int tiles_per_img, int B, double *sums,
                          hipStream_t s);
-int tiles_per_image(int shape, int H, int W);
+int tiles_per_image(int shape, int R, int H, int W);  // residual partials per image
 
 // ---- launchers (eed4_batched.hip) ----
 hipError_t launch_batched_step(int R, int shape, int grid, const ImageDesc *imgs,

@@ -1,0 +1,237 @@
+// Device code of one fused FOEED/FSI inner step on a vertical strip, one
+// wavefront per strip, no workgroup barriers.
+//
+// A wave owns 64 consecutive columns c = X0-2 .. X0+61 (one per lane) and
+// streams down the rows of a segment.  For each input row y it
+//   S1  stages u^k(y, X0-2-R .. X0+61+R) in a per-wave LDS ring (mirrored
+//       indices realise the Neumann condition, Sec. 2.1) and takes the x pass
+//       of the Gaussian presmoothing (Sec. 2.2) at its column;
+//   S2  completes the y pass at row y-R from a register window of the last
+//       2R+1 x-pass values (the row loop is unrolled over that window);
+//   S3  at row g = y-R-1: central-difference gradient of u_sigma (lane
+//       neighbours through DPP wave shifts), fourth-order diffusion tensor
+//       (Sec. 3.1: eigenvalues g, 1, sqrt g), Hessian of u from the LDS ring
+//       (Sec. 3.3 stencils, sign-corrected u_xy) and T = D : H;
+//   S4  at row o = g-1: outer differences of T (eq. genModel), explicit step,
+//       FSI extrapolation (Sec. 3.3), Dirichlet hold; optional FP64 residual.
+// Outputs are the 60 columns X0 .. X0+59 (lanes 2..61).  Every intermediate
+// lives on the mirror-extended image, so P stays symmetric.
+#pragma once
+
+#include "eed4_internal.h"
+
+namespace eed4 {
+
+// Half-sample mirror by repeated reflection (any i, n >= 1).
+__device__ __forceinline__ int mirror_reflect(int i, int n)
+{
+    while (i < 0 || i >= n) i = (i < 0) ? -1 - i : 2 * n - 1 - i;
+    return i;
+}
+
+// Value held by lane+1 / lane-1 (DPP wave shifts; edge lanes read 0).
+__device__ __forceinline__ float from_next_lane(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float from_prev_lane(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
+}
+
+// Orders LDS accesses of different lanes of one wave (a wave executes its LDS
+// instructions in order; this only stops the compiler from reordering them).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+template <int R>
+struct StripGeo {
+    static constexpr int P = 2 * R + 1;                       // y window length
+    static constexpr int U = P * ((R + 3 + P - 1) / P);       // unroll = LDS ring depth
+    static constexpr int D = U;                               // (a multiple of P, >= R+3)
+    static constexpr int h = R + 2;                           // input halo
+    static constexpr int SW = 60;                             // output columns per wave
+    static constexpr int NU = 64 + 2 * R;                     // staged u columns per row
+    static constexpr int M = (68 + U - 1) / U;                // main-loop iterations
+    static constexpr int NROW = 2 * R + M * U;                // rows streamed per wave
+    static constexpr int OH = NROW - 2 * h;                   // output rows per wave
+    static constexpr int LDS = D * NU;                        // floats of LDS per wave
+};
+
+// Per-wave constants of a strip step.
+struct StripArgs {
+    const float *ucur, *uprev;
+    float *uout;
+    const float *ref;           // cycle start for the residual (RES variant only)
+    const uint8_t *mask;
+    int H, W, X0, Y0;
+    float tau, alpha, il2q;     // il2q = 1 / (4 lambda^2)
+};
+
+// base + byte offset (a scalar row base plus a per-lane 32-bit offset)
+template <typename T>
+__device__ __forceinline__ T ldg(const T *base, unsigned byte_off)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+
+template <int R, bool RES>
+__device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
+                                           const float (&w)[2 * kRMax + 1], double *partial)
+{
+    using G = StripGeo<R>;
+    constexpr int P = G::P, U = G::U, D = G::D, NU = G::NU;
+    const int lane = threadIdx.x & 63;
+    const int H = s.H, W = s.W;
+
+    // staged columns (fixed for the whole strip), as byte offsets into a row
+    const unsigned ca = 4u * (unsigned)mirror_reflect(s.X0 - 2 - R + lane, W);
+    const bool has_b = lane < 2 * R;
+    const unsigned cb = has_b ? 4u * (unsigned)mirror_reflect(s.X0 + 62 - R + lane, W) : ca;
+    const int cl = s.X0 - 2 + lane;                           // this lane's column
+    const bool out_lane = lane >= 2 && lane < 62 && cl < W;
+    const unsigned co = out_lane ? (unsigned)cl : 0u;         // element offset in an output row
+
+    float *rl = ring + lane;                                  // row r of the ring at r * NU
+    const int ybase = s.Y0 - G::h;                            // image row of stream row 0
+
+    float win[P];             // x-pass values, row i in slot i % P
+#pragma unroll
+    for (int j = 0; j < P; ++j) win[j] = 0.0f;
+    float v_m1 = 0.0f, v_m2 = 0.0f;                      // v at rows g, g-1 (before update)
+    float txx_p = 0.0f, tyy_p = 0.0f, tyy_pp = 0.0f;     // T at rows g-1 (and g-2 for Tyy)
+    float z_p = 0.0f, z_pp = 0.0f;                       // Txy(l+1)-Txy(l-1) at rows g-1, g-2
+    float uc_p = 0.0f;                                   // u^k(g-1, c)
+    double d2 = 0.0, n2 = 0.0;
+
+    // Global loads of a stream row are issued one row ahead, always in the
+    // same order (u^k row, then the output row's u^{k-1}, mask, reference),
+    // so waiting for one row never waits for the next row's loads.
+    float a_nx, b_nx, pv_nx = 0.0f, rf_nx = 0.0f;
+    unsigned mk_nx = 0;
+    auto prefetch = [&](int i) {
+        const int y = mirror_reflect(ybase + i, H);
+        const float *rowp = s.ucur + (size_t)y * W;
+        a_nx = ldg(rowp, ca);
+        b_nx = ldg(rowp, cb);
+        int o = ybase + i - R - 2;                       // output row served by row i
+        o = o < 0 ? 0 : (o >= H ? H - 1 : o);            // clamped; unused rows are not stored
+        const size_t ro = (size_t)o * W;
+        pv_nx = (s.uprev + ro)[co];
+        mk_nx = (s.mask + ro)[co];
+        if constexpr (RES) rf_nx = (s.ref + ro)[co];
+    };
+    prefetch(0);
+
+    // ---- prologue: stage rows 0 .. 2R-1 and their x pass ----
+#pragma unroll
+    for (int i = 0; i < 2 * R; ++i) {
+        const float a = a_nx, b = b_nx;
+        prefetch(i + 1);
+        float *slot = rl + (i % D) * NU;
+        slot[0] = a;
+        if (has_b) slot[64] = b;
+        wave_lds_sync();
+        float acc = w[0] * slot[0];
+#pragma unroll
+        for (int j = 1; j <= 2 * R; ++j) acc = fmaf(w[j], slot[j], acc);
+        win[i % P] = acc;
+    }
+
+#pragma unroll 1
+    for (int it = 0; it < G::M; ++it) {
+#pragma unroll
+        for (int ph = 0; ph < U; ++ph) {
+            const int i = 2 * R + it * U + ph;           // stream row (wave-uniform)
+            const float a = a_nx, b = b_nx, pv = pv_nx, rf = rf_nx;
+            const unsigned mk = mk_nx;
+            prefetch(i + 1);                              // mirrored: always valid rows
+
+            // ---- S1: stage u^k row i and take the x pass ----
+            float *slot = rl + ((2 * R + ph) % D) * NU;
+            slot[0] = a;
+            if (has_b) slot[64] = b;
+            wave_lds_sync();
+            float acc = w[0] * slot[0];
+#pragma unroll
+            for (int j = 1; j <= 2 * R; ++j) acc = fmaf(w[j], slot[j], acc);
+            win[(2 * R + ph) % P] = acc;
+
+            // ---- S2: y pass at stream row i - R ----
+            float v = w[0] * win[ph % P];
+#pragma unroll
+            for (int j = 1; j <= 2 * R; ++j) v = fmaf(w[j], win[(ph + j) % P], v);
+
+            // ---- S3: gradient, tensor, Hessian, contraction at row g = i - R - 1 ----
+            // (the first rows of the loop produce values that only feed unstored rows)
+            const float gxs = from_next_lane(v_m1) - from_prev_lane(v_m1);  // 2 gx
+            const float gys = v - v_m2;                                      // 2 gy
+            v_m2 = v_m1;
+            v_m1 = v;
+            const float *um = rl + ((R - 2 + ph + D) % D) * NU + R;    // row g - 1
+            const float *u0 = rl + ((R - 1 + ph + D) % D) * NU + R;    // row g
+            const float *up = rl + ((R + ph) % D) * NU + R;            // row g + 1
+            const float uc = u0[0];
+            const float hxx = (u0[-1] - uc) + (u0[1] - uc);
+            const float hyy = (um[0] - uc) + (up[0] - uc);
+            const float hxy = 0.25f * ((up[1] + um[-1]) - (up[-1] + um[1]));
+
+            const float s2 = fmaf(gxs, gxs, gys * gys);                      // 4 |grad|^2
+            const float mu1 = __builtin_amdgcn_rsqf(fmaf(s2, s.il2q, 1.0f));
+            const float mu3 = __builtin_amdgcn_sqrtf(mu1);
+            const float rn = __builtin_amdgcn_rsqf(fmaxf(s2, 1e-30f));
+            const float nx = gxs * rn, ny = gys * rn;   // unit direction (0 where grad = 0)
+            const float aa = nx * nx, bb = ny * ny, c = nx * ny;
+            const float amb = aa - bb, c2 = c + c;
+            const float e1h = fmaf(aa, hxx, fmaf(bb, hyy, c2 * hxy));
+            const float x3 = fmaf(c, hyy - hxx, amb * hxy);
+            const float k1 = fmaf(mu1, e1h, -e1h);
+            const float k3 = fmaf(mu3, x3, -x3);
+            const float k3c2 = k3 * c2;
+            const float txx = fmaf(k1, aa, hxx - k3c2);
+            const float tyy = fmaf(k1, bb, hyy + k3c2);
+            const float txy = fmaf(k1, c, fmaf(k3, amb, hxy));
+            const float z = from_next_lane(txy) - from_prev_lane(txy);
+
+            // ---- S4: output row o = g - 1 (stream row i - R - 2) ----
+            const int o = ybase + i - R - 2;
+            if (i >= 2 * G::h && o < H) {      // first output row of the segment is Y0
+                const float pu = ((from_prev_lane(txx_p) - txx_p) + (from_next_lane(txx_p) - txx_p)) +
+                                 ((tyy_pp - tyy_p) + (tyy - tyy_p)) + 0.5f * (z - z_pp);
+                if (out_lane) {
+                    const float wv = fmaf(-s.tau, pu, uc_p);
+                    float un = fmaf(s.alpha, wv - pv, pv);
+                    if (mk) un = uc_p;
+                    if constexpr (RES) {
+                        const double dd = (double)un - (double)rf;
+                        d2 = fma(dd, dd, d2);
+                        n2 = fma((double)un, (double)un, n2);
+                    }
+                    (s.uout + (size_t)o * W)[co] = un;
+                }
+            }
+            tyy_pp = tyy_p;
+            tyy_p = tyy;
+            txx_p = txx;
+            z_pp = z_p;
+            z_p = z;
+            uc_p = uc;
+        }
+    }
+    if constexpr (RES) {
+        for (int off = 32; off > 0; off >>= 1) {
+            d2 += __shfl_down(d2, off, 64);
+            n2 += __shfl_down(n2, off, 64);
+        }
+        if (lane == 0) {
+            partial[0] = d2;
+            partial[1] = n2;
+        }
+    }
+}
+
+}  // namespace eed4

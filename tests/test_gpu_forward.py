@@ -20,11 +20,14 @@ if not torch.cuda.is_available():
 import paper_2006_10406_amd as eed4  # noqa: E402
 
 
-def gpu_cycle(states, mask, known, lam, sigma, tau, n):
+KERNELS = {"strip": 0, "tile": eed4.EED4_TILE_KERNEL}
+
+
+def gpu_cycle(states, mask, known, lam, sigma, tau, n, flags=0):
     """One eed4_fsi_cycle over a batch of FP32 start states; returns (u, sums)."""
     u = to_dev(states.astype(np.float32))
     sums = torch.zeros((states.shape[0], 2), dtype=torch.float64, device="cuda")
-    p = eed4.params(lam, sigma, tau, n, 1)
+    p = eed4.params(lam, sigma, tau, n, 1, flags=flags)
     eed4.eed4_fsi_cycle(u, to_dev(mask), to_dev(known.astype(np.float32)), p, sums)
     torch.cuda.synchronize()
     return u.cpu().numpy(), sums.cpu().numpy()
@@ -75,12 +78,14 @@ def test_small64_full_run():
     assert np.allclose(hist[:, 0, 1], rh[:, 1], rtol=1e-5)
 
 
+@pytest.mark.parametrize("kernel", ["strip", "tile"])
 @pytest.mark.parametrize("H,W,sigma,lam", [
     (37, 53, 1.0, 0.05), (1, 1, 1.0, 0.1), (1, 100, 1.5, 0.05), (100, 1, 1.5, 0.05),
     (3, 5, 2.0, 0.03), (65, 33, 0.0, 0.1), (70, 130, 0.5, 0.02), (97, 67, 2.6, 0.05),
-    (64, 64, 1.5, 0.03), (33, 129, 2.0, 0.02)])
-def test_ragged_shapes_and_radii(H, W, sigma, lam):
-    announce(f"ragged {H}x{W} sigma={sigma}")
+    (64, 64, 1.5, 0.03), (33, 129, 2.0, 0.02), (230, 190, 2.0, 0.02), (161, 250, 1.0, 0.05),
+    (150, 121, 0.3, 0.04), (140, 200, 2.3, 0.05)])
+def test_ragged_shapes_and_radii(H, W, sigma, lam, kernel):
+    announce(f"ragged {H}x{W} sigma={sigma} kernel={kernel}")
     pr = make_problem(H, W, 3, True, 0.01, 0.1, 77 + H * 1000 + W)
     n, tau = 7, 0.05
     # two cycles: the second starts from a non-trivial state
@@ -88,10 +93,10 @@ def test_ragged_shapes_and_radii(H, W, sigma, lam):
                                  checkpoints=True)
     masks = np.repeat(pr["mask"][None], 2, 0)
     knowns = np.repeat(pr["known"][None], 2, 0)
-    got, _ = gpu_cycle(ck, masks, knowns, lam, sigma, tau, n)
+    got, _ = gpu_cycle(ck, masks, knowns, lam, sigma, tau, n, KERNELS[kernel])
     ref, _ = oracle_cycle(ck, masks, knowns, lam, sigma, tau, n)
     errs = [rel_l2(got[m], ref[m]) for m in range(2)]
-    print(f"{H}x{W} sigma {sigma}: rel L2 {max(errs):.3e}")
+    print(f"{H}x{W} sigma {sigma} {kernel}: rel L2 {max(errs):.3e}")
     assert max(errs) <= REL_L2_PER_CYCLE
 
 
@@ -162,6 +167,20 @@ def test_stop_rule_and_steady_state_512():
     print(f"single512 RMSE vs FP64 at {st.cycles} cycles: {e:.3e} (rel L2 {rel_l2(got, ref):.3e}); "
           f"RMSE vs ground truth {rmse(got, pr['image']):.4f}")
     assert e <= RMSE_STEADY
+
+
+def test_strip_and_tile_kernels_agree():
+    announce("strip vs tile kernel, 300x260, 3 cycles")
+    pr = make_problem(300, 260, 12, True, 0.01, 0.04, 555)
+    outs = []
+    for f in (0, eed4.EED4_TILE_KERNEL):
+        u = to_dev(pr["u_init"])
+        eed4.eed4_inpaint(u, to_dev(pr["mask"]), to_dev(pr["known"]),
+                          eed4.params(0.03, 1.5, 0.05, 15, 3, flags=f))
+        outs.append(u.cpu().numpy())
+    e = rel_l2(outs[0], outs[1])
+    print(f"strip vs tile rel L2 {e:.3e}")
+    assert e <= 1e-6
 
 
 def test_large4096_first_cycle_parity():
