@@ -70,20 +70,4 @@ hipError_t launch_batched_reduce(const ImageDesc *imgs, const double *partials,
                                  const int *tiles_img, int B, double *sums, hipStream_t s);
 int batched_occupancy_grid(int R, int shape);
 
-// ---- launchers (eed4_adjoint.hip) ----
-hipError_t launch_adjoint_a(int R, const float *u, const float *abar_next, const uint8_t *mask,
-                            int B, int H, int W, const StepArgs &a, float *qx, float *qy,
-                            float *pr, double *lam_partials, hipStream_t s);
-hipError_t launch_adjoint_b(int R, const float *qx, const float *qy, const float *pr,
-                            float *abar_next, float *abar_cur, const uint8_t *mask,
-                            float *grad_known, int B, int H, int W, const StepArgs &a,
-                            int first_step, hipStream_t s);
-hipError_t launch_adjoint_final(const float *abar0, const uint8_t *mask, float *grad_known,
-                                float *grad_init, size_t n, hipStream_t s);
-hipError_t launch_lambda_reduce(const double *lam_partials, int tiles_per_img, int B,
-                                double *acc, hipStream_t s);
-hipError_t launch_lambda_store(const double *acc, float *grad_lambda, int B, hipStream_t s);
-hipError_t launch_fill_double(double *p, size_t n, hipStream_t s);
-int adjoint_tiles_per_image(int H, int W);
-
 }  // namespace eed4

@@ -54,6 +54,7 @@ def test_workspace_size(lib):
     assert n1 >= 2 * 64 * 64 * 4
     assert e.eed4_workspace_size(e.EED4_OP_INPAINT, 2, 64, 64, p) > n1
     assert e.eed4_workspace_size(e.EED4_OP_CYCLE, 1, 64, 64, p) >= 2 * 64 * 64 * 4
+    assert e.eed4_workspace_size(e.EED4_OP_BACKWARD, 1, 64, 64, p) > 0
     assert e.eed4_workspace_size(e.EED4_OP_INPAINT, 0, 64, 64, p) == 0
     bad = e.params(-1.0, 1.0, 0.05, 10, 20)
     assert e.eed4_workspace_size(e.EED4_OP_INPAINT, 1, 64, 64, bad) == 0
