@@ -70,6 +70,11 @@ extern "C" {
  * kernel.  Both compute the same step; results agree to rounding. */
 #define EED4_TILE_KERNEL     0x8
 
+/* eed4_inpaint_batched only: use kernel shape s instead of the autotuned one
+ * (0: 64x32 workgroup tiles, 1: 64x16 tiles, 2: 32x32 tiles, 3: wave strips
+ * of 60 columns x about 64 rows, 4: wave strips about twice as tall). */
+#define EED4_FORCE_SHAPE(s)  ((((s) + 1) & 0xff) << 8)
+
 /* ---- workspace sizing (eed4_workspace_size op) ---- */
 #define EED4_OP_INPAINT  1
 #define EED4_OP_CYCLE    2
@@ -175,6 +180,15 @@ size_t eed4_batched_workspace_size(const eed4_image *imgs, int B,
 int eed4_inpaint_batched(const eed4_image *imgs, int B, const eed4_params *p,
                          void *ws, size_t ws_bytes, void *stream,
                          eed4_stats *stats);
+
+/* Autotuner of eed4_inpaint_batched: times one inner step of every kernel
+ * shape on this batch (the caller's u is not modified), remembers the fastest
+ * for batches of this kind (radius, image count, size classes) and returns
+ * its id (>= 0), or a negative EED4_E* code.  eed4_inpaint_batched runs it by
+ * itself on the first call for a kind of batch; with the environment variable
+ * EED4_AUTOTUNE_CACHE naming a file, choices persist across processes. */
+int eed4_autotune_batched(const eed4_image *imgs, int B, const eed4_params *p,
+                          void *ws, size_t ws_bytes, void *stream);
 
 /* Message for a return code. */
 const char *eed4_strerror(int code);

@@ -21,8 +21,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (EED4_ABS_TOL, EED4_ALLOW_LARGE_TAU, EED4_NO_GRAPH, EED4_OP_BACKWARD,
-                   EED4_TILE_KERNEL,
+from ._lib import (EED4_ABS_TOL, EED4_ALLOW_LARGE_TAU, EED4_FORCE_SHAPE, EED4_NO_GRAPH,
+                   EED4_OP_BACKWARD, EED4_TILE_KERNEL, SHAPE_NAMES,
                    EED4_OP_CYCLE, EED4_OP_INPAINT, eed4_image, eed4_params, eed4_stats)
 
 _lib.lib()  # fail loudly at import if libeed4.so is missing
@@ -31,7 +31,8 @@ __all__ = [
     "EED4Error", "params", "eed4_radius", "eed4_workspace_size", "eed4_inpaint",
     "eed4_fsi_cycle", "eed4_fsi_step", "eed4_backward", "eed4_batched_workspace_size", "eed4_inpaint_batched",
     "eed4_strerror", "EED4_ABS_TOL", "EED4_ALLOW_LARGE_TAU", "EED4_NO_GRAPH", "EED4_TILE_KERNEL",
-    "EED4_OP_INPAINT", "EED4_OP_CYCLE", "EED4_OP_BACKWARD", "library_path",
+    "EED4_OP_INPAINT", "EED4_OP_CYCLE", "EED4_OP_BACKWARD", "EED4_FORCE_SHAPE", "SHAPE_NAMES",
+    "eed4_autotune_batched", "library_path",
 ]
 
 
@@ -241,3 +242,18 @@ def eed4_inpaint_batched(images, p: eed4_params, ws: Optional[torch.Tensor] = No
                                          _stream(images[0][0], stream), st)
     _check(rc, "eed4_inpaint_batched")
     return list(st)
+
+
+def eed4_autotune_batched(images, p: eed4_params, ws: Optional[torch.Tensor] = None,
+                          stream=None) -> int:
+    """Run the batched-kernel autotuner on this batch; returns the chosen shape id."""
+    arr, dev = _image_array(images)
+    need = _lib.lib().eed4_batched_workspace_size(arr, len(images), ctypes.byref(p))
+    if need == 0:
+        _check(-1, "eed4_batched_workspace_size")
+    wp, wsz, _hold = _workspace(need, dev, ws)
+    rc = _lib.lib().eed4_autotune_batched(arr, len(images), ctypes.byref(p), wp, wsz,
+                                          _stream(images[0][0], stream))
+    if rc < 0:
+        _check(rc, "eed4_autotune_batched")
+    return rc

@@ -20,6 +20,13 @@ EED4_ABS_TOL = 0x2
 EED4_NO_GRAPH = 0x4
 EED4_TILE_KERNEL = 0x8
 
+
+def EED4_FORCE_SHAPE(s):
+    return ((s + 1) & 0xFF) << 8
+
+
+SHAPE_NAMES = ("tile64x32", "tile64x16", "tile32x32", "strip", "strip_tall")
+
 EED4_OP_INPAINT = 1
 EED4_OP_CYCLE = 2
 EED4_OP_BACKWARD = 3
@@ -27,7 +34,7 @@ EED4_OP_BACKWARD = 3
 EXPORTED = ("eed4_radius", "eed4_workspace_size", "eed4_inpaint", "eed4_fsi_cycle",
             "eed4_fsi_step",
             "eed4_backward", "eed4_batched_workspace_size", "eed4_inpaint_batched",
-            "eed4_strerror")
+            "eed4_autotune_batched", "eed4_strerror")
 
 
 class eed4_params(ctypes.Structure):
@@ -76,6 +83,8 @@ def lib():
         L.eed4_inpaint_batched.restype = i
         L.eed4_inpaint_batched.argtypes = [ctypes.POINTER(eed4_image), i, pp, vp, sz, vp,
                                            ctypes.POINTER(eed4_stats)]
+        L.eed4_autotune_batched.restype = i
+        L.eed4_autotune_batched.argtypes = [ctypes.POINTER(eed4_image), i, pp, vp, sz, vp]
         L.eed4_strerror.restype = ctypes.c_char_p
         L.eed4_strerror.argtypes = [i]
         _L = L

@@ -1,14 +1,699 @@
-// Batched uneven-size inpainting (placeholder until the persistent kernel lands).
+// Batched inpainting of images of uneven sizes: one persistent launch per
+// inner FSI step over a work queue spanning every image, the cycle captured
+// once as a hipGraph, per-image stop, and an autotuner that picks the kernel
+// shape (workgroup tiles or wave strips of two heights) by timing one step on
+// the actual batch.
+//
+// The queue holds one entry per work item (a tile of a workgroup, or a strip
+// segment of a wave) of every image still iterating.  Items are pulled with a
+// global atomic counter (one counter per inner step, cleared by a kernel at
+// the start of the cycle), so a launch balances images of any size without
+// per-image launches.  The queue length lives in device memory: dropping a
+// converged image rewrites the queue without re-capturing the graph.
 #include "eed4.h"
 #include "eed4_host.h"
+#include "eed4_internal.h"
+#include "eed4_strip.h"
+#include "eed4_tile.h"
 
-extern "C" size_t eed4_batched_workspace_size(const eed4_image *, int, const eed4_params *)
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+namespace eed4 {
+
+struct BImage {            // device-side image descriptor
+    float *buf[3];         // S (caller's u), X, Y
+    const uint8_t *mask;
+    int H, W;
+    float inv_lam2;
+    int nx;                // work items per row of items
+};
+
+struct BItem {             // one queue entry
+    int img, iy, ix, slot; // item row / column inside the image; residual slot
+};
+
+__device__ __forceinline__ float *pick(const BImage &d, int sel)
 {
-    return 0;
+    return sel == 0 ? d.buf[0] : (sel == 1 ? d.buf[1] : d.buf[2]);
 }
 
-extern "C" int eed4_inpaint_batched(const eed4_image *, int, const eed4_params *, void *, size_t,
-                                    void *, eed4_stats *)
+// Next queue index for a wave.  Every lane takes part in the atomic (lane 0
+// adds 1, the others 0) and lane 0's result is broadcast: no lane-dependent
+// branch, so the persistent loops keep a uniform structure.
+__device__ __forceinline__ int pull(unsigned *counter)
 {
-    return EED4_EINVAL;
+    const unsigned v = atomicAdd(counter, (threadIdx.x & 63) == 0 ? 1u : 0u);
+    return (int)__builtin_amdgcn_readfirstlane(v);
+}
+
+// Wave-strip shapes: every wave pulls strip segments until the queue is empty.
+template <int R, int MX, bool RES>
+__global__ __launch_bounds__(256) void bstrip_kernel(const BImage *imgs, const BItem *queue,
+                                                     const int *qlen_p, unsigned *counter,
+                                                     int sc, int sp, int so, StepArgs a,
+                                                     double *partials)
+{
+    using G = StripGeo<R, MX>;
+    __shared__ float lds[4 * G::LDS];
+    const int wave = threadIdx.x >> 6;
+    const int qlen = *qlen_p;
+    for (;;) {
+        const int it = pull(counter);
+        if (it >= qlen) break;
+        const BItem t = queue[it];
+        const BImage d = imgs[t.img];
+        StripArgs s;
+        s.ucur = pick(d, sc);
+        s.uprev = pick(d, sp);
+        s.uout = pick(d, so);
+        s.ref = d.buf[0];
+        s.mask = d.mask;
+        s.H = d.H;
+        s.W = d.W;
+        s.X0 = t.ix * G::SW;
+        s.Y0 = t.iy * G::OH;
+        s.tau = a.tau;
+        s.alpha = a.alpha;
+        s.il2q = 0.25f * d.inv_lam2;
+        strip_step<R, RES, MX>(lds + wave * G::LDS, s, a.w, partials + 2 * (size_t)t.slot);
+    }
+}
+
+// Workgroup-tile shapes: every workgroup pulls tiles until the queue is empty.
+template <int R, int TW, int TH>
+__global__ __launch_bounds__(256) void btile_kernel(const BImage *imgs, const BItem *queue,
+                                                    const int *qlen_p, unsigned *counter,
+                                                    int sc, int sp, int so, int residual,
+                                                    StepArgs a, double *partials)
+{
+    __shared__ __attribute__((aligned(16))) float smem[TileGeo<R, TW, TH>::SMEM];
+    __shared__ int s_item;
+    const int qlen = *qlen_p;
+    // Only wave-uniform conditions around the barriers: wave 0 (an SGPR test)
+    // pulls the next tile (lane 0's atomic, broadcast with readfirstlane) and
+    // all its lanes store it; the index read back is made uniform as well.
+    // A thread-0 test here lets the compiler split the loop so that the other
+    // lanes return to the barrier without a new pull.
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (;;) {
+        if (wave == 0) s_item = pull(counter);
+        __syncthreads();           // also ends every use of smem by the previous tile
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();
+        if (it >= qlen) break;
+        const BItem t = queue[it];
+        const BImage d = imgs[t.img];
+        step_tile<R, TW, TH>(smem, pick(d, sc), pick(d, sp), pick(d, so),
+                             residual ? d.buf[0] : nullptr, d.mask, d.H, d.W, t.iy, t.ix, a.w,
+                             a.tau, a.alpha, d.inv_lam2,
+                             residual ? partials + 2 * (size_t)t.slot : nullptr);
+    }
+}
+
+// Copy X -> S over the items of the queue (cycles of length 1 end in X).
+__global__ __launch_bounds__(256) void bcopy_kernel(const BImage *imgs, const BItem *queue,
+                                                    const int *qlen_p, int tw, int th)
+{
+    const int qlen = *qlen_p;
+    for (int it = blockIdx.x; it < qlen; it += gridDim.x) {
+        const BItem t = queue[it];
+        const BImage d = imgs[t.img];
+        const int x0 = t.ix * tw, y0 = t.iy * th;
+        for (int i = threadIdx.x; i < tw * th; i += blockDim.x) {
+            int y = y0 + i / tw, x = x0 + i % tw;
+            if (y < d.H && x < d.W) {
+                size_t gi = (size_t)y * d.W + x;
+                d.buf[0][gi] = d.buf[1][gi];
+            }
+        }
+    }
+}
+
+__global__ void bclear_kernel(unsigned *counters, int n)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) counters[i] = 0u;
+}
+
+// sums[b] = fixed-order sum of the partials of image b's items
+__global__ __launch_bounds__(256) void breduce_kernel(const double *partials, const int *slot0,
+                                                      const int *nslot, double *sums)
+{
+    __shared__ double sd[256], sn[256];
+    const int b = blockIdx.x;
+    const double *p = partials + 2 * (size_t)slot0[b];
+    const int n = nslot[b];
+    double d = 0.0, q = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        d += p[2 * i];
+        q += p[2 * i + 1];
+    }
+    sd[threadIdx.x] = d;
+    sn[threadIdx.x] = q;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            sd[threadIdx.x] += sd[threadIdx.x + s];
+            sn[threadIdx.x] += sn[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        sums[2 * b] = sd[0];
+        sums[2 * b + 1] = sn[0];
+    }
+}
+
+__global__ __launch_bounds__(256) void bhold_kernel(float *u, const uint8_t *__restrict__ mask,
+                                                    const float *__restrict__ known, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        if (mask[i]) u[i] = known[i];
+}
+
+// ---------------------------------------------------------------- host side
+
+// item size of a shape in pixels
+static void item_dims(int shape, int R, int *iw, int *ih)
+{
+    if (shape == kShapeStrip || shape == kShapeStripTall) {
+        *iw = 60;
+        *ih = strip_rows(R, shape == kShapeStripTall ? 2 : 1);
+        return;
+    }
+    *iw = kTileShapes[shape].tw;
+    *ih = kTileShapes[shape].th;
+}
+
+template <int R>
+static hipError_t launch_bstep_r(int shape, int grid, const BImage *imgs, const BItem *queue,
+                                 const int *qlen, unsigned *counter, int sc, int sp, int so,
+                                 bool res, const StepArgs &a, double *partials, hipStream_t s)
+{
+    dim3 g(grid), b(256);
+    switch (shape) {
+    case 0:
+        hipLaunchKernelGGL((btile_kernel<R, 64, 32>), g, b, 0, s, imgs, queue, qlen, counter, sc,
+                           sp, so, res ? 1 : 0, a, partials);
+        break;
+    case 1:
+        hipLaunchKernelGGL((btile_kernel<R, 64, 16>), g, b, 0, s, imgs, queue, qlen, counter, sc,
+                           sp, so, res ? 1 : 0, a, partials);
+        break;
+    case 2:
+        hipLaunchKernelGGL((btile_kernel<R, 32, 32>), g, b, 0, s, imgs, queue, qlen, counter, sc,
+                           sp, so, res ? 1 : 0, a, partials);
+        break;
+    case kShapeStrip:
+        if (res)
+            hipLaunchKernelGGL((bstrip_kernel<R, 1, true>), g, b, 0, s, imgs, queue, qlen,
+                               counter, sc, sp, so, a, partials);
+        else
+            hipLaunchKernelGGL((bstrip_kernel<R, 1, false>), g, b, 0, s, imgs, queue, qlen,
+                               counter, sc, sp, so, a, partials);
+        break;
+    case kShapeStripTall:
+        if (res)
+            hipLaunchKernelGGL((bstrip_kernel<R, 2, true>), g, b, 0, s, imgs, queue, qlen,
+                               counter, sc, sp, so, a, partials);
+        else
+            hipLaunchKernelGGL((bstrip_kernel<R, 2, false>), g, b, 0, s, imgs, queue, qlen,
+                               counter, sc, sp, so, a, partials);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+static hipError_t launch_bstep(int R, int shape, int grid, const BImage *imgs, const BItem *queue,
+                               const int *qlen, unsigned *counter, int sc, int sp, int so, bool res,
+                               const StepArgs &a, double *partials, hipStream_t s)
+{
+    switch (R) {
+#define EED4_CASE(r) \
+    case r: return launch_bstep_r<r>(shape, grid, imgs, queue, qlen, counter, sc, sp, so, res, a, partials, s);
+        EED4_CASE(0) EED4_CASE(1) EED4_CASE(2) EED4_CASE(3) EED4_CASE(4)
+        EED4_CASE(5) EED4_CASE(6) EED4_CASE(7) EED4_CASE(8)
+#undef EED4_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// Persistent grid: enough workgroups to fill every CU at the kernel's occupancy.
+static int persistent_grid(int R, int shape)
+{
+    static std::mutex mu;
+    static std::map<std::pair<int, int>, int> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    auto key = std::make_pair(R, shape);
+    auto f = cache.find(key);
+    if (f != cache.end()) return f->second;
+    int dev = 0, cus = 256, per = 4;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const void *fn = nullptr;
+    switch (shape * 16 + R) {
+#define EED4_FN(sh, r, K) case sh * 16 + r: fn = (const void *)(K); break;
+#define EED4_FNS(r)                                                     \
+    EED4_FN(0, r, (btile_kernel<r, 64, 32>))                            \
+    EED4_FN(1, r, (btile_kernel<r, 64, 16>))                            \
+    EED4_FN(2, r, (btile_kernel<r, 32, 32>))                            \
+    EED4_FN(3, r, (bstrip_kernel<r, 1, false>))                         \
+    EED4_FN(4, r, (bstrip_kernel<r, 2, false>))
+        EED4_FNS(0) EED4_FNS(1) EED4_FNS(2) EED4_FNS(3) EED4_FNS(4)
+        EED4_FNS(5) EED4_FNS(6) EED4_FNS(7) EED4_FNS(8)
+#undef EED4_FNS
+#undef EED4_FN
+    default: break;
+    }
+    if (fn) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, 0) == hipSuccess && nb > 0)
+            per = nb;
+    }
+    int g = cus * per;
+    cache[key] = g;
+    return g;
+}
+
+struct BatchLayout {
+    std::vector<size_t> X, Y;
+    size_t imgs, queue, qlen, counters, partials, slot0, nslot, sums, total;
+};
+
+static int max_items(int B, const eed4_image *im, int R)
+{
+    int m = 0;
+    for (int sh = 0; sh < kNumShapes; ++sh) {
+        long long t = 0;
+        for (int i = 0; i < B; ++i) t += tiles_per_image(sh, R, im[i].H, im[i].W);
+        if (t > m) m = (int)std::min<long long>(t, 0x7fffffff);
+    }
+    return m;
+}
+
+static BatchLayout batch_layout(const eed4_image *im, int B, const eed4_params *p)
+{
+    BatchLayout L;
+    const int R = eed4_radius(p->sigma);
+    size_t o = 0;
+    L.X.resize(B);
+    L.Y.resize(B);
+    for (int i = 0; i < B; ++i) {
+        size_t n = (size_t)im[i].H * im[i].W;
+        L.X[i] = o; o = align_up(o + sizeof(float) * n);
+        L.Y[i] = o; o = align_up(o + sizeof(float) * n);
+    }
+    const size_t items = (size_t)max_items(B, im, R);
+    L.imgs = o; o = align_up(o + sizeof(BImage) * (size_t)B);
+    L.queue = o; o = align_up(o + sizeof(BItem) * items);
+    L.qlen = o; o = align_up(o + sizeof(int));
+    L.counters = o; o = align_up(o + sizeof(unsigned) * (size_t)p->cycle_len);
+    L.partials = o; o = align_up(o + sizeof(double) * 2 * items);
+    L.slot0 = o; o = align_up(o + sizeof(int) * (size_t)B);
+    L.nslot = o; o = align_up(o + sizeof(int) * (size_t)B);
+    L.sums = o; o = align_up(o + sizeof(double) * 2 * (size_t)B);
+    L.total = o;
+    return L;
+}
+
+static int check_images(const eed4_image *im, int B, const eed4_params *p)
+{
+    if (!im || B < 1 || !p) return EED4_EINVAL;
+    for (int i = 0; i < B; ++i) {
+        if (!im[i].u || !im[i].mask || !im[i].known) return EED4_EINVAL;
+        eed4_params q = *p;
+        q.lambda = im[i].lambda;
+        int rc = check_params(&q, 1, im[i].H, im[i].W);
+        if (rc != EED4_OK) return rc;
+    }
+    return EED4_OK;
+}
+
+// Everything a batched run needs on the device, for one kernel shape.
+struct BatchRun {
+    int R, shape, grid, n, B;
+    int iw, ih;                      // item size in pixels
+    std::vector<BImage> himg;
+    std::vector<int> slot0, nslot;   // residual slots per image
+    std::vector<BItem> queue;        // items of the active images
+    BImage *dimg;
+    BItem *dqueue;
+    int *dqlen, *dslot0, *dnslot;
+    unsigned *dcounters;
+    double *dpartials, *dsums;
+    const eed4_params *p;
+};
+
+static void build_queue(BatchRun &r, const std::vector<char> &active)
+{
+    r.queue.clear();
+    for (int i = 0; i < r.B; ++i) {
+        if (!active[i]) continue;
+        const int nx = (r.himg[i].W + r.iw - 1) / r.iw, ny = (r.himg[i].H + r.ih - 1) / r.ih;
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) r.queue.push_back({i, y, x, r.slot0[i] + y * nx + x});
+    }
+}
+
+static int upload_queue(BatchRun &r, hipStream_t s)
+{
+    int ql = (int)r.queue.size();
+    hipError_t e = hipMemcpyAsync(r.dqueue, r.queue.data(), sizeof(BItem) * r.queue.size(),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(r.dqlen, &ql, sizeof(int), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);   // host buffers are stack/vector owned
+    return e == hipSuccess ? EED4_OK : hip_fail(e, "queue upload");
+}
+
+static int prepare(BatchRun &r, const eed4_image *im, int B, const eed4_params *p, int shape,
+                   char *base, const BatchLayout &L, hipStream_t s)
+{
+    r.R = eed4_radius(p->sigma);
+    r.shape = shape;
+    r.n = p->cycle_len;
+    r.B = B;
+    r.p = p;
+    item_dims(shape, r.R, &r.iw, &r.ih);
+    r.grid = persistent_grid(r.R, shape);
+    r.himg.resize(B);
+    r.slot0.resize(B);
+    r.nslot.resize(B);
+    int slot = 0;
+    for (int i = 0; i < B; ++i) {
+        BImage d;
+        d.buf[0] = im[i].u;
+        d.buf[1] = (float *)(base + L.X[i]);
+        d.buf[2] = (float *)(base + L.Y[i]);
+        d.mask = im[i].mask;
+        d.H = im[i].H;
+        d.W = im[i].W;
+        d.inv_lam2 = (float)(1.0 / ((double)im[i].lambda * (double)im[i].lambda));
+        d.nx = (im[i].W + r.iw - 1) / r.iw;
+        r.himg[i] = d;
+        r.slot0[i] = slot;
+        r.nslot[i] = tiles_per_image(shape, r.R, im[i].H, im[i].W);
+        slot += r.nslot[i];
+    }
+    r.dimg = (BImage *)(base + L.imgs);
+    r.dqueue = (BItem *)(base + L.queue);
+    r.dqlen = (int *)(base + L.qlen);
+    r.dslot0 = (int *)(base + L.slot0);
+    r.dnslot = (int *)(base + L.nslot);
+    r.dcounters = (unsigned *)(base + L.counters);
+    r.dpartials = (double *)(base + L.partials);
+    r.dsums = (double *)(base + L.sums);
+    hipError_t e = hipMemcpyAsync(r.dimg, r.himg.data(), sizeof(BImage) * B,
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(r.dslot0, r.slot0.data(), sizeof(int) * B, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(r.dnslot, r.nslot.data(), sizeof(int) * B, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "descriptor upload");
+    std::vector<char> active(B, 1);
+    build_queue(r, active);
+    return upload_queue(r, s);
+}
+
+// Roles of S (0), X (1), Y (2) in step k of a cycle of n (as cycle_roles).
+static void roles(int k, int n, int *sc, int *sp, int *so)
+{
+    if (k == 0) { *sc = 0; *sp = 0; *so = 1; }
+    else {
+        *sc = (k & 1) ? 1 : 2;
+        *sp = (k == 1) ? 0 : ((k & 1) ? 2 : 1);
+        *so = (k & 1) ? 2 : 1;
+    }
+    if (k == n - 1 && n > 1) *so = 0;
+}
+
+static int enqueue_bcycle(const BatchRun &r, hipStream_t s)
+{
+    hipLaunchKernelGGL(bclear_kernel, dim3((r.n + 255) / 256), dim3(256), 0, s, r.dcounters, r.n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "counter clear");
+    for (int k = 0; k < r.n; ++k) {
+        int sc, sp, so;
+        roles(k, r.n, &sc, &sp, &so);
+        StepArgs a = make_args(r.p->sigma, r.R, r.p->tau, 1.0f, k);
+        e = launch_bstep(r.R, r.shape, r.grid, r.dimg, r.dqueue, r.dqlen, r.dcounters + k, sc, sp,
+                         so, k == r.n - 1, a, r.dpartials, s);
+        if (e != hipSuccess) return hip_fail(e, "batched step launch");
+    }
+    if (r.n == 1) {
+        hipLaunchKernelGGL(bcopy_kernel, dim3(1024), dim3(256), 0, s, r.dimg, r.dqueue, r.dqlen,
+                           r.iw, r.ih);
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "batched copy");
+    }
+    hipLaunchKernelGGL(breduce_kernel, dim3(r.B), dim3(256), 0, s, r.dpartials, r.dslot0,
+                       r.dnslot, r.dsums);
+    e = hipGetLastError();
+    return e == hipSuccess ? EED4_OK : hip_fail(e, "batched reduce");
+}
+
+// ---- autotuner ----
+static std::mutex g_tune_mu;
+static std::map<std::string, int> g_tune;
+static bool g_tune_loaded = false;
+
+static std::string tune_key(const eed4_image *im, int B, int R)
+{
+    double px = 0;
+    int minside = 1 << 30, maxside = 0;
+    for (int i = 0; i < B; ++i) {
+        px += (double)im[i].H * im[i].W;
+        minside = std::min(minside, std::min(im[i].H, im[i].W));
+        maxside = std::max(maxside, std::max(im[i].H, im[i].W));
+    }
+    char buf[128];
+    std::snprintf(buf, sizeof(buf), "R%d_B%d_px2^%d_side%d-%d", R, B, (int)std::lround(std::log2(px + 1)),
+                  (int)std::lround(std::log2(minside)), (int)std::lround(std::log2(maxside)));
+    return buf;
+}
+
+static void tune_load()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = std::getenv("EED4_AUTOTUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char key[128];
+    int shape;
+    while (std::fscanf(f, "%127s %d", key, &shape) == 2)
+        if (shape >= 0 && shape < kNumShapes) g_tune[key] = shape;
+    std::fclose(f);
+}
+
+static void tune_store()
+{
+    const char *path = std::getenv("EED4_AUTOTUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "w");
+    if (!f) return;
+    for (auto &kv : g_tune) std::fprintf(f, "%s %d\n", kv.first.c_str(), kv.second);
+    std::fclose(f);
+}
+
+// Times one inner step (k = 0: S -> X, S unchanged) of every shape on the batch.
+static int autotune(const eed4_image *im, int B, const eed4_params *p, char *base,
+                    const BatchLayout &L, hipStream_t s, int *best_shape, float *best_ms)
+{
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return hip_fail(hipErrorInvalidValue, "event");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(hipErrorInvalidValue, "event");
+    }
+    int best = kShapeStrip, rc = EED4_OK;
+    float bt = 1e30f;
+    for (int sh = 0; sh < kNumShapes && rc == EED4_OK; ++sh) {
+        BatchRun r;
+        if ((rc = prepare(r, im, B, p, sh, base, L, s)) != EED4_OK) break;
+        StepArgs a = make_args(p->sigma, r.R, p->tau, 1.0f, 0);
+        float tmin = 1e30f;
+        for (int rep = 0; rep < 3 && rc == EED4_OK; ++rep) {
+            hipLaunchKernelGGL(bclear_kernel, dim3(1), dim3(256), 0, s, r.dcounters, 1);
+            hipError_t e = hipEventRecord(e0, s);
+            if (e == hipSuccess)
+                e = launch_bstep(r.R, sh, r.grid, r.dimg, r.dqueue, r.dqlen, r.dcounters, 0, 0, 1,
+                                 false, a, r.dpartials, s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) rc = hip_fail(e, "autotune timing");
+            else if (rep > 0) tmin = std::min(tmin, ms);   // first run warms up
+        }
+        if (rc == EED4_OK && tmin < bt) {
+            bt = tmin;
+            best = sh;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *best_shape = best;
+    *best_ms = bt;
+    return rc;
+}
+
+static int choose_shape(const eed4_image *im, int B, const eed4_params *p, char *base,
+                        const BatchLayout &L, hipStream_t s, int *shape)
+{
+    const int forced = (p->flags >> 8) & 0xff;
+    if (forced) {
+        if (forced - 1 >= kNumShapes) return EED4_EINVAL;
+        *shape = forced - 1;
+        return EED4_OK;
+    }
+    const std::string key = tune_key(im, B, eed4_radius(p->sigma));
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load();
+        auto f = g_tune.find(key);
+        if (f != g_tune.end()) {
+            *shape = f->second;
+            return EED4_OK;
+        }
+    }
+    float ms = 0.0f;
+    int rc = autotune(im, B, p, base, L, s, shape, &ms);
+    if (rc != EED4_OK) return rc;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = *shape;
+    tune_store();
+    return EED4_OK;
+}
+
+}  // namespace eed4
+
+using namespace eed4;
+
+extern "C" size_t eed4_batched_workspace_size(const eed4_image *imgs, int B, const eed4_params *p)
+{
+    if (check_images(imgs, B, p) != EED4_OK) return 0;
+    return batch_layout(imgs, B, p).total;
+}
+
+extern "C" int eed4_autotune_batched(const eed4_image *imgs, int B, const eed4_params *p,
+                                     void *ws, size_t ws_bytes, void *stream)
+{
+    int rc = check_images(imgs, B, p);
+    if (rc != EED4_OK) return rc;
+    BatchLayout L = batch_layout(imgs, B, p);
+    if ((rc = check_ws(ws, ws_bytes, L.total)) != EED4_OK) return rc;
+    int shape = 0;
+    float ms = 0.0f;
+    rc = autotune(imgs, B, p, (char *)ws, L, (hipStream_t)stream, &shape, &ms);
+    if (rc != EED4_OK) return rc;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load();
+    g_tune[tune_key(imgs, B, eed4_radius(p->sigma))] = shape;
+    tune_store();
+    return shape;
+}
+
+extern "C" int eed4_inpaint_batched(const eed4_image *imgs, int B, const eed4_params *p, void *ws,
+                                    size_t ws_bytes, void *stream, eed4_stats *stats)
+{
+    int rc = check_images(imgs, B, p);
+    if (rc != EED4_OK) return rc;
+    BatchLayout L = batch_layout(imgs, B, p);
+    if ((rc = check_ws(ws, ws_bytes, L.total)) != EED4_OK) return rc;
+    char *base = (char *)ws;
+    hipStream_t s = (hipStream_t)stream;
+
+    for (int i = 0; i < B; ++i) {
+        size_t n = (size_t)imgs[i].H * imgs[i].W;
+        unsigned g = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+        hipLaunchKernelGGL(bhold_kernel, dim3(g), dim3(256), 0, s, imgs[i].u, imgs[i].mask,
+                           imgs[i].known, n);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "hold launch");
+
+    int shape = kShapeStrip;
+    if ((rc = choose_shape(imgs, B, p, base, L, s, &shape)) != EED4_OK) return rc;
+    BatchRun r;
+    if ((rc = prepare(r, imgs, B, p, shape, base, L, s)) != EED4_OK) return rc;
+
+    hipGraphExec_t exec = nullptr;
+    if (!(p->flags & EED4_NO_GRAPH)) {
+        hipStream_t cs = capture_stream();
+        if (!cs) return hip_fail(hipErrorInvalidValue, "capture stream");
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "begin capture");
+        rc = enqueue_bcycle(r, cs);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(cs, &g);
+        if (rc != EED4_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "end capture");
+        e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+    }
+
+    const int M = p->max_cycles;
+    std::vector<char> active(B, 1);
+    std::vector<double> host(2 * (size_t)B);
+    std::vector<eed4_stats> st(B);
+    for (int i = 0; i < B; ++i) st[i] = {0, 0.0, 0.0};
+    int nactive = B;
+    bool diverged = false;
+    for (int m = 0; m < M && nactive > 0 && rc == EED4_OK; ++m) {
+        if (exec) {
+            e = hipGraphLaunch(exec, s);
+            if (e != hipSuccess) { rc = hip_fail(e, "graph launch"); break; }
+        } else if ((rc = enqueue_bcycle(r, s)) != EED4_OK) {
+            break;
+        }
+        const bool need = p->tol > 0.0f || m == M - 1;
+        if (!need) {
+            for (int i = 0; i < B; ++i)
+                if (active[i]) st[i].cycles = m + 1;
+            continue;
+        }
+        e = hipMemcpyAsync(host.data(), r.dsums, sizeof(double) * 2 * B, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { rc = hip_fail(e, "residual read-back"); break; }
+        bool changed = false;
+        for (int i = 0; i < B; ++i) {
+            if (!active[i]) continue;
+            const double res = std::sqrt(host[2 * i]), nn = std::sqrt(host[2 * i + 1]);
+            st[i].cycles = m + 1;
+            st[i].residual = res;
+            st[i].rel_residual = nn > 0.0 ? res / nn : res;
+            if (!std::isfinite(res) || !std::isfinite(nn)) diverged = true;
+            const double crit = (p->flags & EED4_ABS_TOL) ? st[i].residual : st[i].rel_residual;
+            if (p->tol > 0.0f && crit < (double)p->tol) {
+                active[i] = 0;
+                --nactive;
+                changed = true;
+            }
+        }
+        if (diverged) break;
+        if (changed && nactive > 0) {
+            build_queue(r, active);
+            rc = upload_queue(r, s);
+        }
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (rc != EED4_OK) return rc;
+    if (stats)
+        for (int i = 0; i < B; ++i) stats[i] = st[i];
+    return diverged ? EED4_EDIVERGED : EED4_OK;
 }

@@ -106,17 +106,30 @@ hipError_t launch_hold(float *u, const uint8_t *mask, const float *known, size_t
 }
 
 template <int R>
-static int strip_items(int H, int W)
+static int strip_items(int H, int W, int mx)
 {
-    using G = StripGeo<R>;
-    return ((W + G::SW - 1) / G::SW) * ((H + G::OH - 1) / G::OH);
+    const int OH = mx == 2 ? StripGeo<R, 2>::OH : StripGeo<R, 1>::OH;
+    const int SW = StripGeo<R, 1>::SW;
+    return ((W + SW - 1) / SW) * ((H + OH - 1) / OH);
+}
+
+int strip_rows(int R, int mx)
+{
+    switch (R) {
+#define EED4_CASE(r) case r: return mx == 2 ? StripGeo<r, 2>::OH : StripGeo<r, 1>::OH;
+        EED4_CASE(0) EED4_CASE(1) EED4_CASE(2) EED4_CASE(3) EED4_CASE(4)
+        EED4_CASE(5) EED4_CASE(6) EED4_CASE(7) EED4_CASE(8)
+#undef EED4_CASE
+    default: return 0;
+    }
 }
 
 int tiles_per_image(int shape, int R, int H, int W)
 {
-    if (shape == kShapeStrip) {
+    if (shape == kShapeStrip || shape == kShapeStripTall) {
+        const int mx = shape == kShapeStripTall ? 2 : 1;
         switch (R) {
-#define EED4_CASE(r) case r: return strip_items<r>(H, W);
+#define EED4_CASE(r) case r: return strip_items<r>(H, W, mx);
             EED4_CASE(0) EED4_CASE(1) EED4_CASE(2) EED4_CASE(3) EED4_CASE(4)
             EED4_CASE(5) EED4_CASE(6) EED4_CASE(7) EED4_CASE(8)
 #undef EED4_CASE

@@ -29,8 +29,9 @@ struct TileShape {
 // wave-strip kernel (60 columns x a radius-dependent row count per wave).
 constexpr int kNumTileShapes = 3;
 constexpr TileShape kTileShapes[kNumTileShapes] = {{64, 32}, {64, 16}, {32, 32}};
-constexpr int kShapeStrip = 3;
-constexpr int kNumShapes = 4;
+constexpr int kShapeStrip = 3;       // ~64 output rows per wave
+constexpr int kShapeStripTall = 4;   // ~2x the rows per wave (batched path only)
+constexpr int kNumShapes = 5;
 
 // Device-side descriptor of one image of an uneven batch.
 struct ImageDesc {
@@ -59,15 +60,6 @@ hipError_t launch_step(int R, int shape, const float *ucur, const float *uprev, 
 hipError_t launch_reduce(const double *partials, int tiles_per_img, int B, double *sums,
                          hipStream_t s);
 int tiles_per_image(int shape, int R, int H, int W);  // residual partials per image
-
-// ---- launchers (eed4_batched.hip) ----
-hipError_t launch_batched_step(int R, int shape, int grid, const ImageDesc *imgs,
-                               const TileRef *queue, const int *qlen, unsigned *counter,
-                               int sel_cur, int sel_prev, int sel_out, int residual,
-                               const StepArgs &a, double *partials, hipStream_t s);
-hipError_t launch_reset_counter(unsigned *counter, hipStream_t s);
-hipError_t launch_batched_reduce(const ImageDesc *imgs, const double *partials,
-                                 const int *tiles_img, int B, double *sums, hipStream_t s);
-int batched_occupancy_grid(int R, int shape);
+int strip_rows(int R, int mx);                         // output rows per strip segment
 
 }  // namespace eed4

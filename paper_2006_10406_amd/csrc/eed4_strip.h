@@ -39,6 +39,15 @@ __device__ __forceinline__ float from_prev_lane(float v)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
 }
 
+// Lane 0's value of a double, wave-uniform.
+__device__ __forceinline__ double lane0_double(double x)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, 0);
+    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), 0);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Orders LDS accesses of different lanes of one wave (a wave executes its LDS
 // instructions in order; this only stops the compiler from reordering them).
 __device__ __forceinline__ void wave_lds_sync()
@@ -48,7 +57,9 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
 }
 
-template <int R>
+// MX scales the segment height (rows per wave): MX = 1 gives about 64 output
+// rows, MX = 2 about twice that.
+template <int R, int MX = 1>
 struct StripGeo {
     static constexpr int P = 2 * R + 1;                       // y window length
     static constexpr int U = P * ((R + 3 + P - 1) / P);       // unroll = LDS ring depth
@@ -56,7 +67,7 @@ struct StripGeo {
     static constexpr int h = R + 2;                           // input halo
     static constexpr int SW = 60;                             // output columns per wave
     static constexpr int NU = 64 + 2 * R;                     // staged u columns per row
-    static constexpr int M = (68 + U - 1) / U;                // main-loop iterations
+    static constexpr int M = MX * ((68 + U - 1) / U);         // main-loop iterations
     static constexpr int NROW = 2 * R + M * U;                // rows streamed per wave
     static constexpr int OH = NROW - 2 * h;                   // output rows per wave
     static constexpr int LDS = D * NU;                        // floats of LDS per wave
@@ -79,11 +90,11 @@ __device__ __forceinline__ T ldg(const T *base, unsigned byte_off)
     return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
 }
 
-template <int R, bool RES>
+template <int R, bool RES, int MX = 1>
 __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
                                            const float (&w)[2 * kRMax + 1], double *partial)
 {
-    using G = StripGeo<R>;
+    using G = StripGeo<R, MX>;
     constexpr int P = G::P, U = G::U, D = G::D, NU = G::NU;
     const int lane = threadIdx.x & 63;
     const int H = s.H, W = s.W;
@@ -227,10 +238,11 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
             d2 += __shfl_down(d2, off, 64);
             n2 += __shfl_down(n2, off, 64);
         }
-        if (lane == 0) {
-            partial[0] = d2;
-            partial[1] = n2;
-        }
+        // lane 0 holds the sums; every lane stores that same value (no
+        // lane-dependent branch at the end of a persistent loop body)
+        const double d2s = lane0_double(d2), n2s = lane0_double(n2);
+        partial[0] = d2s;
+        partial[1] = n2s;
     }
 }
 
