@@ -16,6 +16,7 @@ The JSON line carries:
              rocprofv3 counter summary when it matches the current kernel
   cpu_baseline  the FP64 oracle on the host cores, one cycle of the same image
   adjoint_forward_ratio  backward/forward time on 16 x 256 x 256 (30 cycles of 10)
+  batched    64 uneven images: one batched call vs 64 single-image calls
 """
 import argparse
 import hashlib
@@ -72,6 +73,11 @@ def cpu_baseline(pr, wl):
                       f"FP64, {dt:.1f} s"}
 
 
+def aligned_workspace(torch, nbytes, dev):
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    return buf[(-buf.data_ptr()) % 256:]
+
+
 def adjoint_ratio(eed4, torch, args):
     """Forward (with per-cycle checkpoints) vs backward time on 16 x 256 x 256."""
     from synth import WORKLOADS, make_batch
@@ -88,17 +94,17 @@ def adjoint_ratio(eed4, torch, args):
     gk = torch.empty_like(gu)
     gi = torch.empty_like(gu)
     gl = torch.empty(B, device=dev)
-    wsf = torch.empty(eed4.eed4_workspace_size(eed4.EED4_OP_INPAINT, B, H, W, p) + 256,
-                      dtype=torch.uint8, device=dev)
-    wsb = torch.empty(eed4.eed4_workspace_size(eed4.EED4_OP_BACKWARD, B, H, W, p) + 256,
-                      dtype=torch.uint8, device=dev)
+    wsf = aligned_workspace(torch, eed4.eed4_workspace_size(eed4.EED4_OP_INPAINT, B, H, W, p), dev)
+    wsb = aligned_workspace(torch, eed4.eed4_workspace_size(eed4.EED4_OP_BACKWARD, B, H, W, p),
+                            dev)
+    u = u0.clone()
 
     def fwd():
-        u = u0.clone()
-        eed4.eed4_inpaint(u, mask, known, p, ckpt=ck)
+        u.copy_(u0)
+        eed4.eed4_inpaint(u, mask, known, p, ckpt=ck, ws=wsf)
 
     def bwd():
-        eed4.eed4_backward(ck, mask, known, p, wl.M, gu, gk, gi, gl)
+        eed4.eed4_backward(ck, mask, known, p, wl.M, gu, gk, gi, gl, ws=wsb)
 
     def timed(fn, reps):
         fn()
@@ -138,6 +144,51 @@ def probe(eed4, torch, u_init, mask, wl):
     log(f"probe done: {3 * wl.n} step launches, one copy of {src.numel() * 4} bytes")
 
 
+def batched_vs_single(eed4, torch, cycles):
+    """64 uneven images (sides U{128..1024}, 2..8% masks, sigma 1.5, lambda 0.03,
+    n 15): one eed4_inpaint_batched call (autotuned persistent kernels, graph)
+    against 64 eed4_inpaint calls, same cycle count; throughput in
+    Mpixel-updates/s and the largest RMSE between the two results."""
+    from synth import WORKLOADS, make_uneven_batch
+    wl = WORKLOADS["batch64"]
+    probs = make_uneven_batch(wl)
+    dev = "cuda"
+    inits = [torch.from_numpy(p["u_init"]).to(dev) for p in probs]
+    masks = [torch.from_numpy(p["mask"]).to(dev) for p in probs]
+    knowns = [torch.from_numpy(p["known"]).to(dev) for p in probs]
+    px = sum(p["u_init"].size for p in probs)
+    p = eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, cycles)
+    # warm both paths (the first batched call also runs the autotuner)
+    us = [u.clone() for u in inits]
+    eed4.eed4_inpaint_batched([(u, m, k, wl.lam) for u, m, k in zip(us, masks, knowns)],
+                              eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, 1))
+    u0 = inits[0].clone()
+    eed4.eed4_inpaint(u0, masks[0], knowns[0], eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, 1))
+    torch.cuda.synchronize()
+
+    ub = [u.clone() for u in inits]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    eed4.eed4_inpaint_batched([(u, m, k, wl.lam) for u, m, k in zip(ub, masks, knowns)], p)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    shape = eed4.eed4_autotune_batched([(u, m, k, wl.lam) for u, m, k in zip(ub, masks, knowns)],
+                                       p)
+    us = [u.clone() for u in inits]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for u, m, k in zip(us, masks, knowns):
+        eed4.eed4_inpaint(u, m, k, p)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    diff = max(float(torch.sqrt(torch.mean((a - b) ** 2))) for a, b in zip(ub, us))
+    upd = px * wl.n * cycles
+    return {"workload": f"batch64: 64 images, {px} px, {cycles} cycles of {wl.n}",
+            "batched_mpix_updates_s": upd / tb / 1e6, "per_image_mpix_updates_s": upd / ts / 1e6,
+            "speedup": ts / tb, "batched_ms": tb * 1e3, "per_image_ms": ts * 1e3,
+            "autotuned_shape": eed4.SHAPE_NAMES[shape], "max_rmse_between": diff}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +198,8 @@ def main():
                     help="cycles of back-to-back eed4_fsi_step launches for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-cycles", type=int, default=40)
     ap.add_argument("--probe", action="store_true",
                     help="counter probe: 3 cycles of fused step launches on the workload, then "
                          "a plain 64 MiB device copy (calibrates FETCH_SIZE / WRITE_SIZE)")
@@ -173,9 +226,7 @@ def main():
     H, W, n = wl.H, wl.W, wl.n
     pw = eed4.params(wl.lam, wl.sigma, wl.tau, n, max(args.warmup, 1))
     pt = eed4.params(wl.lam, wl.sigma, wl.tau, n, args.steps)
-    ws = torch.empty(eed4.eed4_workspace_size(eed4.EED4_OP_INPAINT, 1, H, W, pt) + 256,
-                     dtype=torch.uint8, device=dev)
-    wsv = ws[(-ws.data_ptr()) % 256:]
+    wsv = aligned_workspace(torch, eed4.eed4_workspace_size(eed4.EED4_OP_INPAINT, 1, H, W, pt), dev)
 
     if args.probe:
         probe(eed4, torch, u_init, mask, wl)
@@ -259,11 +310,11 @@ def main():
                      "kernel_source_sha": kernel_source_sha()},
     }
     if not args.no_adjoint:
-        try:
-            out["adjoint_forward_ratio"] = adjoint_ratio(eed4, torch, args)
-        except eed4.EED4Error as ex:
-            log(f"adjoint ratio unavailable: {ex}")
-            out["adjoint_forward_ratio"] = None
+        log("adjoint / forward timing (16 x 256x256)")
+        out["adjoint_forward_ratio"] = adjoint_ratio(eed4, torch, args)
+    if not args.no_batched:
+        log("batched vs per-image (64 uneven images)")
+        out["batched"] = batched_vs_single(eed4, torch, args.batched_cycles)
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host (one cycle)")
         out["cpu_baseline"] = cpu_baseline(pr, wl)
