@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 
 BYTES_PER_UPDATE = 13          # 4 (u^k) + 4 (u^{k-1}) + 4 (u^{k+1}) + 1 (mask)
 HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
-KERNEL_SOURCES = ("paper_2006_10406_amd/csrc/eed4_tile.h",
+KERNEL_SOURCES = ("paper_2006_10406_amd/csrc/eed4_strip.h",
                   "paper_2006_10406_amd/csrc/eed4_forward.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_large4096_traffic.json")
 
@@ -304,7 +304,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "step_kernel<6,64,32>",
+                     "traffic": traffic, "kernel": "strip_kernel<6,false> (fused FSI step)",
                      "kernel_us": round(kms * 1e3, 2),
                      "algorithmic_bytes_per_launch": per_launch_bytes,
                      "kernel_source_sha": kernel_source_sha()},
