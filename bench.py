@@ -30,6 +30,15 @@ sys.path.insert(0, ROOT)
 
 BYTES_PER_UPDATE = 13          # 4 (u^k) + 4 (u^{k-1}) + 4 (u^{k+1}) + 1 (mask)
 HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
+# FP32 FMA peak without packed FP32: 256 CUs x 64 lanes x 2.4 GHz x 2 flop
+ALU_PEAK_TFLOPS = 256 * 64 * 2.4e9 * 2 / 1e12
+
+
+def flops_per_update(R):
+    """Algorithmic FP32 flops of one pixel-update (FMA = 2): separable blur
+    4(2R+1), gradient 2, tensor 15, Hessian 11, contraction 24, outer
+    differences 13, FSI update and hold 5."""
+    return 4 * (2 * R + 1) + 70
 KERNEL_SOURCES = ("paper_2006_10406_amd/csrc/eed4_strip.h",
                   "paper_2006_10406_amd/csrc/eed4_forward.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_large4096_traffic.json")
@@ -282,8 +291,11 @@ def main():
     kms = e2.elapsed_time(e3) / launches
     per_launch_bytes = BYTES_PER_UPDATE * H * W
     achieved = per_launch_bytes / (kms * 1e-3) / 1e9
+    R = eed4.eed4_radius(wl.sigma)
+    per_launch_flops = flops_per_update(R) * H * W
+    tflops = per_launch_flops / (kms * 1e-3) / 1e12
     traffic = measured_traffic(H * W)
-    log(f"fused step kernel: {kms * 1e3:.1f} us/launch, {achieved:.0f} GB/s algorithmic")
+    log(f"fused step kernel: {kms * 1e3:.1f} us/launch, {achieved:.0f} GB/s, {tflops:.1f} TFLOP/s")
 
     out = {
         "metric": "Mpixel-updates/s of fused 4th-order EED FSI step + adjoint/forward time ratio",
@@ -302,11 +314,14 @@ def main():
                    "lambda": wl.lam, "tau": wl.tau, "cycle_len": n, "mask_density": wl.density,
                    "step": "one FSI cycle (15 fused inner steps + FP64 residual)",
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "roofline": {"bound": "alu", "achieved": round(tflops, 2), "peak": round(ALU_PEAK_TFLOPS, 1),
+                     "unit": "TFLOP/s", "frac": round(tflops / ALU_PEAK_TFLOPS, 4),
                      "traffic": traffic, "kernel": "strip_kernel<6,false> (fused FSI step)",
                      "kernel_us": round(kms * 1e3, 2),
-                     "algorithmic_bytes_per_launch": per_launch_bytes,
+                     "algorithmic_flops_per_launch": per_launch_flops,
+                     "hbm": {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(achieved / HBM_PEAK_GBS, 4),
+                             "algorithmic_bytes_per_launch": per_launch_bytes},
                      "kernel_source_sha": kernel_source_sha()},
     }
     if not args.no_adjoint:
