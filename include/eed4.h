@@ -70,9 +70,11 @@ extern "C" {
  * kernel.  Both compute the same step; results agree to rounding. */
 #define EED4_TILE_KERNEL     0x8
 
-/* eed4_inpaint_batched only: use kernel shape s instead of the autotuned one
- * (0: 64x32 workgroup tiles, 1: 64x16 tiles, 2: 32x32 tiles, 3: wave strips
- * of 60 columns x about 64 rows, 4: wave strips about twice as tall). */
+/* Use kernel shape s for the fused step instead of the automatic choice
+ * (the autotuner in eed4_inpaint_batched, a work-size rule elsewhere):
+ * 0: 64x32 workgroup tiles, 1: 64x16 tiles, 2: 32x32 tiles, 3: wave strips of
+ * 60 columns x >= 64 rows, 4: strips of >= 136 rows, 5: strips of >= 28 rows.
+ * All strip heights give bitwise the same results; so do all tile shapes. */
 #define EED4_FORCE_SHAPE(s)  ((((s) + 1) & 0xff) << 8)
 
 /* ---- workspace sizing (eed4_workspace_size op) ---- */

@@ -491,7 +491,7 @@ extern "C" int eed4_backward(const float *ckpt, const uint8_t *mask, const float
     float *qx = (float *)(base + L.qx), *qy = (float *)(base + L.qy), *pr = (float *)(base + L.pr);
     double *lp = (double *)(base + L.lp), *acc = (double *)(base + L.acc);
     const int tpi = adjoint_tiles_per_image(H, W);
-    const int shape = step_shape(p);
+    const int shape = step_shape(p, B, H, W);
     hipError_t e;
 #define EED4_TRY(x, what)                                    \
     do {                                                     \

@@ -7,7 +7,9 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -34,6 +36,7 @@ int check_params(const eed4_params *p, int B, int H, int W)
     if (!(p->tau > 0.0f) || !std::isfinite(p->tau)) return EED4_EINVAL;
     if (p->cycle_len < 1 || p->max_cycles < 1) return EED4_EINVAL;
     if (!(p->tol >= 0.0f) || !std::isfinite(p->tol)) return EED4_EINVAL;
+    if (((p->flags >> 8) & 0xff) > kNumShapes) return EED4_EINVAL;
     if (!(p->flags & EED4_ALLOW_LARGE_TAU) && (double)p->tau > 1.0 / 16.0) return EED4_EUNSTABLE;
     return EED4_OK;
 }
@@ -166,10 +169,111 @@ InpaintLayout inpaint_layout(int op, int B, int H, int W, int R, int M)
     return L;
 }
 
-// Fused step kernel used by the single-image / equal-size-batch entry points.
-int step_shape(const eed4_params *p)
+// ---- autotuner choice cache ----
+static std::mutex g_tune_mu;
+static std::map<std::string, int> g_tune;
+static bool g_tune_loaded = false;
+
+static void tune_load_locked()
 {
-    return (p->flags & EED4_TILE_KERNEL) ? 0 : kShapeStrip;
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = std::getenv("EED4_AUTOTUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char key[160];
+    int shape;
+    while (std::fscanf(f, "%159s %d", key, &shape) == 2)
+        if (shape >= 0 && shape < kNumShapes) g_tune[key] = shape;
+    std::fclose(f);
+}
+
+bool tune_lookup(const std::string &key, int *shape)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    auto it = g_tune.find(key);
+    if (it == g_tune.end()) return false;
+    *shape = it->second;
+    return true;
+}
+
+void tune_remember(const std::string &key, int shape)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    g_tune[key] = shape;
+    const char *path = std::getenv("EED4_AUTOTUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "w");
+    if (!f) return;
+    for (auto &kv : g_tune) std::fprintf(f, "%s %d\n", kv.first.c_str(), kv.second);
+    std::fclose(f);
+}
+
+std::string single_tune_key(int R, int B, int H, int W)
+{
+    char buf[96];
+    std::snprintf(buf, sizeof(buf), "single_R%d_B%d_H%d_W%d", R, B, H, W);
+    return buf;
+}
+
+// Fused step kernel of the single-image / equal-size-batch entry points:
+// EED4_FORCE_SHAPE, else EED4_TILE_KERNEL, else the autotuned choice for this
+// problem size, else tiles for problems too small for strips and strips
+// otherwise.  All strip shapes give bitwise the same result, as do all tile
+// shapes; strips and tiles agree to rounding.
+int step_shape(const eed4_params *p, int B, int H, int W)
+{
+    const int forced = (p->flags >> 8) & 0xff;
+    if (forced >= 1 && forced <= kNumShapes) return forced - 1;
+    if (p->flags & EED4_TILE_KERNEL) return 0;
+    const int R = eed4_radius(p->sigma);
+    int shape;
+    if (tune_lookup(single_tune_key(R, B, H, W), &shape)) return shape;
+    const long long waves = (long long)tiles_per_image(kShapeStrip, R, H, W) * B;
+    return waves < kMinStripWaves ? 2 : kShapeStrip;
+}
+
+// Times one inner step (k = 0, S -> X; S is not modified) of every shape and
+// remembers the fastest for this problem size.
+int tune_single_step(const eed4_params *p, int B, int H, int W, float *S, float *X,
+                     const uint8_t *mask, hipStream_t s, int *shape)
+{
+    const int R = eed4_radius(p->sigma);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return hip_fail(e, "event");
+    }
+    const StepArgs a = make_args(p->sigma, R, p->tau, p->lambda, 0);
+    int best = kShapeStrip;
+    float bt = 1e30f;
+    for (int sh = 0; sh < kNumShapes && e == hipSuccess; ++sh) {
+        float tmin = 1e30f;
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+            e = hipEventRecord(e0, s);
+            if (e == hipSuccess) e = launch_step(R, sh, S, S, X, nullptr, mask, B, H, W, a, nullptr, s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && rep > 0) tmin = std::fmin(tmin, ms);   // first run warms up
+        }
+        if (e == hipSuccess && tmin < bt) {
+            bt = tmin;
+            best = sh;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "step autotune");
+    *shape = best;
+    tune_remember(single_tune_key(R, B, H, W), best);
+    return EED4_OK;
 }
 
 int check_ws(void *ws, size_t ws_bytes, size_t need)
@@ -195,6 +299,7 @@ int eed4_radius(float sigma)
 size_t eed4_workspace_size(int op, int B, int H, int W, const eed4_params *p)
 {
     if (check_params(p, B, H, W) == EED4_EINVAL) return 0;
+    if (((p->flags >> 8) & 0xff) > kNumShapes) return 0;
     if (op == EED4_OP_INPAINT || op == EED4_OP_CYCLE)
         return inpaint_layout(op, B, H, W, eed4_radius(p->sigma), p->max_cycles).total;
     if (op == EED4_OP_BACKWARD) return backward_workspace(B, H, W, p);
@@ -217,13 +322,17 @@ int eed4_inpaint(float *u, const uint8_t *mask, const float *known, int B, int H
 
     CycleJob j;
     j.S = u; j.X = (float *)(base + L.X); j.Y = (float *)(base + L.Y);
-    j.mask = mask; j.B = B; j.H = H; j.W = W; j.R = R; j.shape = step_shape(p); j.n = p->cycle_len;
+    j.mask = mask; j.B = B; j.H = H; j.W = W; j.R = R; j.shape = step_shape(p, B, H, W); j.n = p->cycle_len;
     j.sigma = p->sigma; j.tau = p->tau; j.lambda = p->lambda;
     j.partials = (double *)(base + L.partials); j.sums = (double *)(base + L.sums);
     double *hist_dev = (double *)(base + L.hist);
 
     hipError_t e = launch_hold(u, mask, known, N, s);
     if (e != hipSuccess) return hip_fail(e, "hold launch");
+    if (!((p->flags >> 8) & 0xff) && !(p->flags & EED4_TILE_KERNEL) &&
+        !tune_lookup(single_tune_key(R, B, H, W), &j.shape)) {
+        if ((rc = tune_single_step(p, B, H, W, u, j.X, mask, s, &j.shape)) != EED4_OK) return rc;
+    }
 
     hipGraphExec_t exec = nullptr;
     if (!(p->flags & EED4_NO_GRAPH)) {
@@ -297,7 +406,7 @@ int eed4_fsi_cycle(float *u, const uint8_t *mask, const float *known, int B, int
     hipStream_t s = (hipStream_t)stream;
     CycleJob j;
     j.S = u; j.X = (float *)(base + L.X); j.Y = (float *)(base + L.Y);
-    j.mask = mask; j.B = B; j.H = H; j.W = W; j.R = eed4_radius(p->sigma); j.shape = step_shape(p);
+    j.mask = mask; j.B = B; j.H = H; j.W = W; j.R = eed4_radius(p->sigma); j.shape = step_shape(p, B, H, W);
     j.n = p->cycle_len; j.sigma = p->sigma; j.tau = p->tau; j.lambda = p->lambda;
     j.partials = (double *)(base + L.partials); j.sums = d_sums;
     hipError_t e = launch_hold(u, mask, known, (size_t)B * H * W, s);
@@ -316,7 +425,7 @@ int eed4_fsi_step(const float *ucur, const float *uprev, float *uout, const uint
     if (o0 < c0 + bytes && c0 < o0 + bytes) return EED4_EINVAL;
     const int R = eed4_radius(p->sigma);
     StepArgs a = make_args(p->sigma, R, p->tau, p->lambda, k);
-    hipError_t e = launch_step(R, step_shape(p), ucur, uprev, uout, nullptr, mask, B, H, W, a, nullptr,
+    hipError_t e = launch_step(R, step_shape(p, B, H, W), ucur, uprev, uout, nullptr, mask, B, H, W, a, nullptr,
                                (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "fsi step launch");
     return EED4_OK;

@@ -5,11 +5,13 @@
 // the actual batch.
 //
 // The queue holds one entry per work item (a tile of a workgroup, or a strip
-// segment of a wave) of every image still iterating.  Items are pulled with a
-// global atomic counter (one counter per inner step, cleared by a kernel at
-// the start of the cycle), so a launch balances images of any size without
-// per-image launches.  The queue length lives in device memory: dropping a
-// converged image rewrites the queue without re-capturing the graph.
+// segment of a wave) of every image still iterating.  A launch keeps a fixed
+// set of resident workgroups that walk the queue with a static stride; every
+// XCD takes contiguous runs of items, so neighbouring items share its L2.  (A
+// global atomic work counter was tried first: with one device-scope counter
+// for all XCDs the pulls serialise and the step took twice as long.)  The
+// queue length lives in device memory: dropping a converged image rewrites the
+// queue without re-capturing the graph.
 #include "eed4.h"
 #include "eed4_host.h"
 #include "eed4_internal.h"
@@ -45,29 +47,20 @@ __device__ __forceinline__ float *pick(const BImage &d, int sel)
     return sel == 0 ? d.buf[0] : (sel == 1 ? d.buf[1] : d.buf[2]);
 }
 
-// Next queue index for a wave.  Every lane takes part in the atomic (lane 0
-// adds 1, the others 0) and lane 0's result is broadcast: no lane-dependent
-// branch, so the persistent loops keep a uniform structure.
-__device__ __forceinline__ int pull(unsigned *counter)
-{
-    const unsigned v = atomicAdd(counter, (threadIdx.x & 63) == 0 ? 1u : 0u);
-    return (int)__builtin_amdgcn_readfirstlane(v);
-}
-
-// Wave-strip shapes: every wave pulls strip segments until the queue is empty.
-template <int R, int MX, bool RES>
+// Wave-strip shapes: wave w of the launch takes items w, w + nw, w + 2 nw, ...
+// (w counted in XCD-contiguous order).
+template <int R, int ROWS, bool RES>
 __global__ __launch_bounds__(256) void bstrip_kernel(const BImage *imgs, const BItem *queue,
-                                                     const int *qlen_p, unsigned *counter,
-                                                     int sc, int sp, int so, StepArgs a,
-                                                     double *partials)
+                                                     const int *qlen_p, int sc, int sp, int so,
+                                                     StepArgs a, double *partials)
 {
-    using G = StripGeo<R, MX>;
+    using G = StripGeo<R, ROWS>;
     __shared__ float lds[4 * G::LDS];
     const int wave = threadIdx.x >> 6;
+    const int nw = 4 * gridDim.x;
+    const int w0 = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + wave);
     const int qlen = *qlen_p;
-    for (;;) {
-        const int it = pull(counter);
-        if (it >= qlen) break;
+    for (int it = w0; it < qlen; it += nw) {
         const BItem t = queue[it];
         const BImage d = imgs[t.img];
         StripArgs s;
@@ -83,32 +76,20 @@ __global__ __launch_bounds__(256) void bstrip_kernel(const BImage *imgs, const B
         s.tau = a.tau;
         s.alpha = a.alpha;
         s.il2q = 0.25f * d.inv_lam2;
-        strip_step<R, RES, MX>(lds + wave * G::LDS, s, a.w, partials + 2 * (size_t)t.slot);
+        strip_step<R, RES, ROWS>(lds + wave * G::LDS, s, a.w, partials + 2 * (size_t)t.slot);
     }
 }
 
-// Workgroup-tile shapes: every workgroup pulls tiles until the queue is empty.
+// Workgroup-tile shapes: workgroup g takes tiles g, g + G, g + 2 G, ...
 template <int R, int TW, int TH>
 __global__ __launch_bounds__(256) void btile_kernel(const BImage *imgs, const BItem *queue,
-                                                    const int *qlen_p, unsigned *counter,
-                                                    int sc, int sp, int so, int residual,
-                                                    StepArgs a, double *partials)
+                                                    const int *qlen_p, int sc, int sp, int so,
+                                                    int residual, StepArgs a, double *partials)
 {
     __shared__ __attribute__((aligned(16))) float smem[TileGeo<R, TW, TH>::SMEM];
-    __shared__ int s_item;
     const int qlen = *qlen_p;
-    // Only wave-uniform conditions around the barriers: wave 0 (an SGPR test)
-    // pulls the next tile (lane 0's atomic, broadcast with readfirstlane) and
-    // all its lanes store it; the index read back is made uniform as well.
-    // A thread-0 test here lets the compiler split the loop so that the other
-    // lanes return to the barrier without a new pull.
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (;;) {
-        if (wave == 0) s_item = pull(counter);
-        __syncthreads();           // also ends every use of smem by the previous tile
-        const int it = __builtin_amdgcn_readfirstlane(s_item);
-        __syncthreads();
-        if (it >= qlen) break;
+    for (int it = xcd_tile(blockIdx.x, gridDim.x); it < qlen; it += gridDim.x) {
+        __syncthreads();           // the previous tile's last LDS reads are done
         const BItem t = queue[it];
         const BImage d = imgs[t.img];
         step_tile<R, TW, TH>(smem, pick(d, sc), pick(d, sp), pick(d, so),
@@ -135,12 +116,6 @@ __global__ __launch_bounds__(256) void bcopy_kernel(const BImage *imgs, const BI
             }
         }
     }
-}
-
-__global__ void bclear_kernel(unsigned *counters, int n)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) counters[i] = 0u;
 }
 
 // sums[b] = fixed-order sum of the partials of image b's items
@@ -185,9 +160,9 @@ __global__ __launch_bounds__(256) void bhold_kernel(float *u, const uint8_t *__r
 // item size of a shape in pixels
 static void item_dims(int shape, int R, int *iw, int *ih)
 {
-    if (shape == kShapeStrip || shape == kShapeStripTall) {
-        *iw = 60;
-        *ih = strip_rows(R, shape == kShapeStripTall ? 2 : 1);
+    if (is_strip(shape)) {
+        *iw = StripGeo<0>::SW;
+        *ih = strip_rows(R, shape);
         return;
     }
     *iw = kTileShapes[shape].tw;
@@ -196,51 +171,41 @@ static void item_dims(int shape, int R, int *iw, int *ih)
 
 template <int R>
 static hipError_t launch_bstep_r(int shape, int grid, const BImage *imgs, const BItem *queue,
-                                 const int *qlen, unsigned *counter, int sc, int sp, int so,
-                                 bool res, const StepArgs &a, double *partials, hipStream_t s)
+                                 const int *qlen, int sc, int sp, int so, bool res,
+                                 const StepArgs &a, double *partials, hipStream_t s)
 {
     dim3 g(grid), b(256);
+#define EED4_BTILE(TW, TH)                                                                    \
+    hipLaunchKernelGGL((btile_kernel<R, TW, TH>), g, b, 0, s, imgs, queue, qlen, sc, sp, so, \
+                       res ? 1 : 0, a, partials)
+#define EED4_BSTRIP(ROWS)                                                                    \
+    if (res)                                                                                 \
+        hipLaunchKernelGGL((bstrip_kernel<R, ROWS, true>), g, b, 0, s, imgs, queue, qlen, sc, \
+                           sp, so, a, partials);                                             \
+    else                                                                                     \
+        hipLaunchKernelGGL((bstrip_kernel<R, ROWS, false>), g, b, 0, s, imgs, queue, qlen,   \
+                           sc, sp, so, a, partials)
     switch (shape) {
-    case 0:
-        hipLaunchKernelGGL((btile_kernel<R, 64, 32>), g, b, 0, s, imgs, queue, qlen, counter, sc,
-                           sp, so, res ? 1 : 0, a, partials);
-        break;
-    case 1:
-        hipLaunchKernelGGL((btile_kernel<R, 64, 16>), g, b, 0, s, imgs, queue, qlen, counter, sc,
-                           sp, so, res ? 1 : 0, a, partials);
-        break;
-    case 2:
-        hipLaunchKernelGGL((btile_kernel<R, 32, 32>), g, b, 0, s, imgs, queue, qlen, counter, sc,
-                           sp, so, res ? 1 : 0, a, partials);
-        break;
-    case kShapeStrip:
-        if (res)
-            hipLaunchKernelGGL((bstrip_kernel<R, 1, true>), g, b, 0, s, imgs, queue, qlen,
-                               counter, sc, sp, so, a, partials);
-        else
-            hipLaunchKernelGGL((bstrip_kernel<R, 1, false>), g, b, 0, s, imgs, queue, qlen,
-                               counter, sc, sp, so, a, partials);
-        break;
-    case kShapeStripTall:
-        if (res)
-            hipLaunchKernelGGL((bstrip_kernel<R, 2, true>), g, b, 0, s, imgs, queue, qlen,
-                               counter, sc, sp, so, a, partials);
-        else
-            hipLaunchKernelGGL((bstrip_kernel<R, 2, false>), g, b, 0, s, imgs, queue, qlen,
-                               counter, sc, sp, so, a, partials);
-        break;
+    case 0: EED4_BTILE(64, 32); break;
+    case 1: EED4_BTILE(64, 16); break;
+    case 2: EED4_BTILE(32, 32); break;
+    case kShapeStrip: EED4_BSTRIP(64); break;
+    case kShapeStripTall: EED4_BSTRIP(136); break;
+    case kShapeStripShort: EED4_BSTRIP(28); break;
     default: return hipErrorInvalidValue;
     }
+#undef EED4_BTILE
+#undef EED4_BSTRIP
     return hipGetLastError();
 }
 
 static hipError_t launch_bstep(int R, int shape, int grid, const BImage *imgs, const BItem *queue,
-                               const int *qlen, unsigned *counter, int sc, int sp, int so, bool res,
+                               const int *qlen, int sc, int sp, int so, bool res,
                                const StepArgs &a, double *partials, hipStream_t s)
 {
     switch (R) {
 #define EED4_CASE(r) \
-    case r: return launch_bstep_r<r>(shape, grid, imgs, queue, qlen, counter, sc, sp, so, res, a, partials, s);
+    case r: return launch_bstep_r<r>(shape, grid, imgs, queue, qlen, sc, sp, so, res, a, partials, s);
         EED4_CASE(0) EED4_CASE(1) EED4_CASE(2) EED4_CASE(3) EED4_CASE(4)
         EED4_CASE(5) EED4_CASE(6) EED4_CASE(7) EED4_CASE(8)
 #undef EED4_CASE
@@ -267,8 +232,9 @@ static int persistent_grid(int R, int shape)
     EED4_FN(0, r, (btile_kernel<r, 64, 32>))                            \
     EED4_FN(1, r, (btile_kernel<r, 64, 16>))                            \
     EED4_FN(2, r, (btile_kernel<r, 32, 32>))                            \
-    EED4_FN(3, r, (bstrip_kernel<r, 1, false>))                         \
-    EED4_FN(4, r, (bstrip_kernel<r, 2, false>))
+    EED4_FN(3, r, (bstrip_kernel<r, 64, false>))                        \
+    EED4_FN(4, r, (bstrip_kernel<r, 136, false>))                       \
+    EED4_FN(5, r, (bstrip_kernel<r, 28, false>))
         EED4_FNS(0) EED4_FNS(1) EED4_FNS(2) EED4_FNS(3) EED4_FNS(4)
         EED4_FNS(5) EED4_FNS(6) EED4_FNS(7) EED4_FNS(8)
 #undef EED4_FNS
@@ -287,7 +253,7 @@ static int persistent_grid(int R, int shape)
 
 struct BatchLayout {
     std::vector<size_t> X, Y;
-    size_t imgs, queue, qlen, counters, partials, slot0, nslot, sums, total;
+    size_t imgs, queue, qlen, partials, slot0, nslot, sums, total;
 };
 
 static int max_items(int B, const eed4_image *im, int R)
@@ -317,7 +283,6 @@ static BatchLayout batch_layout(const eed4_image *im, int B, const eed4_params *
     L.imgs = o; o = align_up(o + sizeof(BImage) * (size_t)B);
     L.queue = o; o = align_up(o + sizeof(BItem) * items);
     L.qlen = o; o = align_up(o + sizeof(int));
-    L.counters = o; o = align_up(o + sizeof(unsigned) * (size_t)p->cycle_len);
     L.partials = o; o = align_up(o + sizeof(double) * 2 * items);
     L.slot0 = o; o = align_up(o + sizeof(int) * (size_t)B);
     L.nslot = o; o = align_up(o + sizeof(int) * (size_t)B);
@@ -349,7 +314,6 @@ struct BatchRun {
     BImage *dimg;
     BItem *dqueue;
     int *dqlen, *dslot0, *dnslot;
-    unsigned *dcounters;
     double *dpartials, *dsums;
     const eed4_params *p;
 };
@@ -409,7 +373,6 @@ static int prepare(BatchRun &r, const eed4_image *im, int B, const eed4_params *
     r.dqlen = (int *)(base + L.qlen);
     r.dslot0 = (int *)(base + L.slot0);
     r.dnslot = (int *)(base + L.nslot);
-    r.dcounters = (unsigned *)(base + L.counters);
     r.dpartials = (double *)(base + L.partials);
     r.dsums = (double *)(base + L.sums);
     hipError_t e = hipMemcpyAsync(r.dimg, r.himg.data(), sizeof(BImage) * B,
@@ -421,6 +384,10 @@ static int prepare(BatchRun &r, const eed4_image *im, int B, const eed4_params *
     if (e != hipSuccess) return hip_fail(e, "descriptor upload");
     std::vector<char> active(B, 1);
     build_queue(r, active);
+    // resident workgroups: no more than the work (4 strip items per workgroup)
+    const int ql = (int)r.queue.size();
+    const int need = is_strip(shape) ? (ql + 3) / 4 : ql;
+    r.grid = std::max(1, std::min(r.grid, need));
     return upload_queue(r, s);
 }
 
@@ -438,14 +405,12 @@ static void roles(int k, int n, int *sc, int *sp, int *so)
 
 static int enqueue_bcycle(const BatchRun &r, hipStream_t s)
 {
-    hipLaunchKernelGGL(bclear_kernel, dim3((r.n + 255) / 256), dim3(256), 0, s, r.dcounters, r.n);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "counter clear");
+    hipError_t e;
     for (int k = 0; k < r.n; ++k) {
         int sc, sp, so;
         roles(k, r.n, &sc, &sp, &so);
         StepArgs a = make_args(r.p->sigma, r.R, r.p->tau, 1.0f, k);
-        e = launch_bstep(r.R, r.shape, r.grid, r.dimg, r.dqueue, r.dqlen, r.dcounters + k, sc, sp,
+        e = launch_bstep(r.R, r.shape, r.grid, r.dimg, r.dqueue, r.dqlen, sc, sp,
                          so, k == r.n - 1, a, r.dpartials, s);
         if (e != hipSuccess) return hip_fail(e, "batched step launch");
     }
@@ -461,12 +426,8 @@ static int enqueue_bcycle(const BatchRun &r, hipStream_t s)
     return e == hipSuccess ? EED4_OK : hip_fail(e, "batched reduce");
 }
 
-// ---- autotuner ----
-static std::mutex g_tune_mu;
-static std::map<std::string, int> g_tune;
-static bool g_tune_loaded = false;
-
-static std::string tune_key(const eed4_image *im, int B, int R)
+// ---- autotuner (the choice cache is shared with the single-image path) ----
+static std::string batch_tune_key(const eed4_image *im, int B, int R)
 {
     double px = 0;
     int minside = 1 << 30, maxside = 0;
@@ -476,34 +437,10 @@ static std::string tune_key(const eed4_image *im, int B, int R)
         maxside = std::max(maxside, std::max(im[i].H, im[i].W));
     }
     char buf[128];
-    std::snprintf(buf, sizeof(buf), "R%d_B%d_px2^%d_side%d-%d", R, B, (int)std::lround(std::log2(px + 1)),
-                  (int)std::lround(std::log2(minside)), (int)std::lround(std::log2(maxside)));
+    std::snprintf(buf, sizeof(buf), "batched_R%d_B%d_px2^%d_side2^%d-%d", R, B,
+                  (int)std::lround(std::log2(px + 1)), (int)std::lround(std::log2(minside)),
+                  (int)std::lround(std::log2(maxside)));
     return buf;
-}
-
-static void tune_load()
-{
-    if (g_tune_loaded) return;
-    g_tune_loaded = true;
-    const char *path = std::getenv("EED4_AUTOTUNE_CACHE");
-    if (!path) return;
-    FILE *f = std::fopen(path, "r");
-    if (!f) return;
-    char key[128];
-    int shape;
-    while (std::fscanf(f, "%127s %d", key, &shape) == 2)
-        if (shape >= 0 && shape < kNumShapes) g_tune[key] = shape;
-    std::fclose(f);
-}
-
-static void tune_store()
-{
-    const char *path = std::getenv("EED4_AUTOTUNE_CACHE");
-    if (!path) return;
-    FILE *f = std::fopen(path, "w");
-    if (!f) return;
-    for (auto &kv : g_tune) std::fprintf(f, "%s %d\n", kv.first.c_str(), kv.second);
-    std::fclose(f);
 }
 
 // Times one inner step (k = 0: S -> X, S unchanged) of every shape on the batch.
@@ -524,10 +461,9 @@ static int autotune(const eed4_image *im, int B, const eed4_params *p, char *bas
         StepArgs a = make_args(p->sigma, r.R, p->tau, 1.0f, 0);
         float tmin = 1e30f;
         for (int rep = 0; rep < 3 && rc == EED4_OK; ++rep) {
-            hipLaunchKernelGGL(bclear_kernel, dim3(1), dim3(256), 0, s, r.dcounters, 1);
             hipError_t e = hipEventRecord(e0, s);
             if (e == hipSuccess)
-                e = launch_bstep(r.R, sh, r.grid, r.dimg, r.dqueue, r.dqlen, r.dcounters, 0, 0, 1,
+                e = launch_bstep(r.R, sh, r.grid, r.dimg, r.dqueue, r.dqlen, 0, 0, 1,
                                  false, a, r.dpartials, s);
             if (e == hipSuccess) e = hipEventRecord(e1, s);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -553,26 +489,16 @@ static int choose_shape(const eed4_image *im, int B, const eed4_params *p, char 
 {
     const int forced = (p->flags >> 8) & 0xff;
     if (forced) {
-        if (forced - 1 >= kNumShapes) return EED4_EINVAL;
+        if (forced > kNumShapes) return EED4_EINVAL;
         *shape = forced - 1;
         return EED4_OK;
     }
-    const std::string key = tune_key(im, B, eed4_radius(p->sigma));
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        tune_load();
-        auto f = g_tune.find(key);
-        if (f != g_tune.end()) {
-            *shape = f->second;
-            return EED4_OK;
-        }
-    }
+    const std::string key = batch_tune_key(im, B, eed4_radius(p->sigma));
+    if (tune_lookup(key, shape)) return EED4_OK;
     float ms = 0.0f;
     int rc = autotune(im, B, p, base, L, s, shape, &ms);
     if (rc != EED4_OK) return rc;
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[key] = *shape;
-    tune_store();
+    tune_remember(key, *shape);
     return EED4_OK;
 }
 
@@ -597,10 +523,7 @@ extern "C" int eed4_autotune_batched(const eed4_image *imgs, int B, const eed4_p
     float ms = 0.0f;
     rc = autotune(imgs, B, p, (char *)ws, L, (hipStream_t)stream, &shape, &ms);
     if (rc != EED4_OK) return rc;
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    tune_load();
-    g_tune[tune_key(imgs, B, eed4_radius(p->sigma))] = shape;
-    tune_store();
+    tune_remember(batch_tune_key(imgs, B, eed4_radius(p->sigma)), shape);
     return shape;
 }
 

@@ -34,14 +34,14 @@ __global__ __launch_bounds__(256) void step_kernel(const float *ucur, const floa
                          partials ? partials + 2 * (size_t)tile : nullptr);
 }
 
-template <int R, bool RES>
+template <int R, bool RES, int ROWS>
 __global__ __launch_bounds__(256) void strip_kernel(const float *ucur, const float *uprev,
                                                     float *uout, const float *ref,
                                                     const uint8_t *__restrict__ mask, int H, int W,
                                                     int nstrip, int per_img, int nitems, StepArgs a,
                                                     double *partials)
 {
-    using G = StripGeo<R>;
+    using G = StripGeo<R, ROWS>;
     __shared__ float lds[4 * G::LDS];
     const int wave = threadIdx.x >> 6;
     // wave-uniform: keep the work item (and all that derives from it) in SGPRs
@@ -64,7 +64,8 @@ __global__ __launch_bounds__(256) void strip_kernel(const float *ucur, const flo
     s.tau = a.tau;
     s.alpha = a.alpha;
     s.il2q = 0.25f * a.inv_lam2;
-    strip_step<R, RES>(lds + wave * G::LDS, s, a.w, RES ? partials + 2 * (size_t)item : nullptr);
+    strip_step<R, RES, ROWS>(lds + wave * G::LDS, s, a.w,
+                             RES ? partials + 2 * (size_t)item : nullptr);
 }
 
 // sums[b] = fixed-order sum of the residual partials of image b's tiles.
@@ -106,17 +107,19 @@ hipError_t launch_hold(float *u, const uint8_t *mask, const float *known, size_t
 }
 
 template <int R>
-static int strip_items(int H, int W, int mx)
+static int strip_oh(int shape)
 {
-    const int OH = mx == 2 ? StripGeo<R, 2>::OH : StripGeo<R, 1>::OH;
-    const int SW = StripGeo<R, 1>::SW;
-    return ((W + SW - 1) / SW) * ((H + OH - 1) / OH);
+    switch (shape) {
+    case kShapeStripTall: return StripGeo<R, 136>::OH;
+    case kShapeStripShort: return StripGeo<R, 28>::OH;
+    default: return StripGeo<R, 64>::OH;
+    }
 }
 
-int strip_rows(int R, int mx)
+int strip_rows(int R, int shape)
 {
     switch (R) {
-#define EED4_CASE(r) case r: return mx == 2 ? StripGeo<r, 2>::OH : StripGeo<r, 1>::OH;
+#define EED4_CASE(r) case r: return strip_oh<r>(shape);
         EED4_CASE(0) EED4_CASE(1) EED4_CASE(2) EED4_CASE(3) EED4_CASE(4)
         EED4_CASE(5) EED4_CASE(6) EED4_CASE(7) EED4_CASE(8)
 #undef EED4_CASE
@@ -126,36 +129,31 @@ int strip_rows(int R, int mx)
 
 int tiles_per_image(int shape, int R, int H, int W)
 {
-    if (shape == kShapeStrip || shape == kShapeStripTall) {
-        const int mx = shape == kShapeStripTall ? 2 : 1;
-        switch (R) {
-#define EED4_CASE(r) case r: return strip_items<r>(H, W, mx);
-            EED4_CASE(0) EED4_CASE(1) EED4_CASE(2) EED4_CASE(3) EED4_CASE(4)
-            EED4_CASE(5) EED4_CASE(6) EED4_CASE(7) EED4_CASE(8)
-#undef EED4_CASE
-        default: return 0;
-        }
+    if (is_strip(shape)) {
+        const int oh = strip_rows(R, shape), sw = StripGeo<0>::SW;
+        if (oh <= 0) return 0;
+        return ((W + sw - 1) / sw) * ((H + oh - 1) / oh);
     }
     const TileShape ts = kTileShapes[shape];
     return ((W + ts.tw - 1) / ts.tw) * ((H + ts.th - 1) / ts.th);
 }
 
-template <int R>
+template <int R, int ROWS>
 static hipError_t launch_strip_t(const float *ucur, const float *uprev, float *uout,
                                  const float *ref, const uint8_t *mask, int B, int H, int W,
                                  const StepArgs &a, double *partials, hipStream_t s)
 {
-    using G = StripGeo<R>;
+    using G = StripGeo<R, ROWS>;
     const int nstrip = (W + G::SW - 1) / G::SW;
     const int per_img = nstrip * ((H + G::OH - 1) / G::OH);
     const long long nitems = (long long)per_img * B;
     const long long nblk = (nitems + 3) / 4;
     if (nitems <= 0 || nblk > 0x7fffffffLL) return hipErrorInvalidValue;
     if (ref)
-        hipLaunchKernelGGL((strip_kernel<R, true>), dim3((unsigned)nblk), dim3(256), 0, s, ucur,
+        hipLaunchKernelGGL((strip_kernel<R, true, ROWS>), dim3((unsigned)nblk), dim3(256), 0, s, ucur,
                            uprev, uout, ref, mask, H, W, nstrip, per_img, (int)nitems, a, partials);
     else
-        hipLaunchKernelGGL((strip_kernel<R, false>), dim3((unsigned)nblk), dim3(256), 0, s, ucur,
+        hipLaunchKernelGGL((strip_kernel<R, false, ROWS>), dim3((unsigned)nblk), dim3(256), 0, s, ucur,
                            uprev, uout, ref, mask, H, W, nstrip, per_img, (int)nitems, a, partials);
     return hipGetLastError();
 }
@@ -183,7 +181,9 @@ static hipError_t launch_step_r(int shape, const float *ucur, const float *uprev
     case 0: return launch_step_t<R, 64, 32>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
     case 1: return launch_step_t<R, 64, 16>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
     case 2: return launch_step_t<R, 32, 32>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
-    case kShapeStrip: return launch_strip_t<R>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
+    case kShapeStrip: return launch_strip_t<R, 64>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
+    case kShapeStripTall: return launch_strip_t<R, 136>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
+    case kShapeStripShort: return launch_strip_t<R, 28>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -23,7 +23,20 @@ int hip_fail(hipError_t e, const char *where);
 size_t align_up(size_t x);
 int check_params(const eed4_params *p, int B, int H, int W);
 int check_ws(void *ws, size_t ws_bytes, size_t need);
-int step_shape(const eed4_params *p);
+int step_shape(const eed4_params *p, int B, int H, int W);
+
+// Without a tuned choice, the single-image path uses workgroup tiles when
+// the default strips would give fewer waves than this (too few to fill the
+// chip), and strips otherwise.
+constexpr long long kMinStripWaves = 2048;
+
+// Autotuner choice cache (process-wide; persisted to the file named by
+// EED4_AUTOTUNE_CACHE when set).
+bool tune_lookup(const std::string &key, int *shape);
+void tune_remember(const std::string &key, int shape);
+std::string single_tune_key(int R, int B, int H, int W);
+int tune_single_step(const eed4_params *p, int B, int H, int W, float *S, float *X,
+                     const uint8_t *mask, hipStream_t s, int *shape);
 StepArgs make_args(float sigma, int R, float tau, float lambda, int k);
 hipStream_t capture_stream();
 void cycle_roles(int k, int n, float *S, float *X, float *Y, float **cur, float **prev,

@@ -29,9 +29,15 @@ struct TileShape {
 // wave-strip kernel (60 columns x a radius-dependent row count per wave).
 constexpr int kNumTileShapes = 3;
 constexpr TileShape kTileShapes[kNumTileShapes] = {{64, 32}, {64, 16}, {32, 32}};
-constexpr int kShapeStrip = 3;       // ~64 output rows per wave
-constexpr int kShapeStripTall = 4;   // ~2x the rows per wave (batched path only)
-constexpr int kNumShapes = 5;
+constexpr int kShapeStrip = 3;       // wave strips of >= 64 output rows
+constexpr int kShapeStripTall = 4;   // >= 136 rows
+constexpr int kShapeStripShort = 5;  // >= 28 rows (more waves for small images)
+constexpr int kNumShapes = 6;
+constexpr bool is_strip(int shape) { return shape >= kShapeStrip && shape < kNumShapes; }
+constexpr int strip_target_rows(int shape)
+{
+    return shape == kShapeStripTall ? 136 : (shape == kShapeStripShort ? 28 : 64);
+}
 
 // Device-side descriptor of one image of an uneven batch.
 struct ImageDesc {
@@ -60,6 +66,6 @@ hipError_t launch_step(int R, int shape, const float *ucur, const float *uprev, 
 hipError_t launch_reduce(const double *partials, int tiles_per_img, int B, double *sums,
                          hipStream_t s);
 int tiles_per_image(int shape, int R, int H, int W);  // residual partials per image
-int strip_rows(int R, int mx);                         // output rows per strip segment
+int strip_rows(int R, int shape);                      // output rows per strip segment
 
 }  // namespace eed4

@@ -57,9 +57,9 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
 }
 
-// MX scales the segment height (rows per wave): MX = 1 gives about 64 output
-// rows, MX = 2 about twice that.
-template <int R, int MX = 1>
+// ROWS is the least number of output rows of a wave's segment (the segment
+// is rounded up to whole unrolled iterations).
+template <int R, int ROWS = 64>
 struct StripGeo {
     static constexpr int P = 2 * R + 1;                       // y window length
     static constexpr int U = P * ((R + 3 + P - 1) / P);       // unroll = LDS ring depth
@@ -67,7 +67,7 @@ struct StripGeo {
     static constexpr int h = R + 2;                           // input halo
     static constexpr int SW = 60;                             // output columns per wave
     static constexpr int NU = 64 + 2 * R;                     // staged u columns per row
-    static constexpr int M = MX * ((68 + U - 1) / U);         // main-loop iterations
+    static constexpr int M = (ROWS + 4 + U - 1) / U;          // main-loop iterations
     static constexpr int NROW = 2 * R + M * U;                // rows streamed per wave
     static constexpr int OH = NROW - 2 * h;                   // output rows per wave
     static constexpr int LDS = D * NU;                        // floats of LDS per wave
@@ -90,11 +90,11 @@ __device__ __forceinline__ T ldg(const T *base, unsigned byte_off)
     return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
 }
 
-template <int R, bool RES, int MX = 1>
+template <int R, bool RES, int ROWS = 64>
 __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
                                            const float (&w)[2 * kRMax + 1], double *partial)
 {
-    using G = StripGeo<R, MX>;
+    using G = StripGeo<R, ROWS>;
     constexpr int P = G::P, U = G::U, D = G::D, NU = G::NU;
     const int lane = threadIdx.x & 63;
     const int H = s.H, W = s.W;

@@ -20,7 +20,7 @@ if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 import paper_2006_10406_amd as eed4  # noqa: E402
 
-SHAPES = range(5)
+SHAPES = range(6)
 SIZES = [(1, 1), (3, 200), (130, 70), (256, 300), (64, 64), (17, 33), (200, 9), (95, 181)]
 LAMS = [0.05, 0.03, 0.02, 0.04, 0.05, 0.1, 0.03, 0.06]
 
@@ -56,7 +56,7 @@ def test_each_shape_equals_single_image_runs(shape):
     sigma, tau, n, M = 1.5, 0.05, 7, 3
     p = eed4.params(1.0, sigma, tau, n, M, flags=eed4.EED4_FORCE_SHAPE(shape))
     outs, st = run_batched(probs, LAMS, p)
-    single_flags = 0 if shape >= 3 else eed4.EED4_TILE_KERNEL
+    single_flags = eed4.EED4_FORCE_SHAPE(shape)
     for i, pr in enumerate(probs):
         ref, _ = run_single(pr, LAMS[i], sigma, tau, n, M, flags=single_flags)
         assert st[i].cycles == M
@@ -70,7 +70,7 @@ def test_short_cycles_batched(n):
     p = eed4.params(1.0, 1.0, 0.05, n, 2, flags=eed4.EED4_FORCE_SHAPE(3))
     outs, _ = run_batched(probs, LAMS[:4], p)
     for i, pr in enumerate(probs):
-        ref, _ = run_single(pr, LAMS[i], 1.0, 0.05, n, 2)
+        ref, _ = run_single(pr, LAMS[i], 1.0, 0.05, n, 2, flags=eed4.EED4_FORCE_SHAPE(3))
         assert np.array_equal(outs[i], ref)
 
 
@@ -83,7 +83,8 @@ def test_per_image_stop_matches_single_runs():
     outs, st = run_batched(probs, lams, p)
     cyc = []
     for i, pr in enumerate(probs):
-        ref, s1 = run_single(pr, lams[i], sigma, tau, n, M, tol=tol)
+        ref, s1 = run_single(pr, lams[i], sigma, tau, n, M, tol=tol,
+                             flags=eed4.EED4_FORCE_SHAPE(5))
         cyc.append((st[i].cycles, s1.cycles))
         assert st[i].cycles == s1.cycles
         assert np.array_equal(outs[i], ref)
@@ -100,7 +101,7 @@ def test_autotune_and_default_path():
     before = [t[0].clone() for t in imgs]
     shape = eed4.eed4_autotune_batched(imgs, p)
     print(f"autotuned shape: {eed4.SHAPE_NAMES[shape]}")
-    assert 0 <= shape < 5
+    assert 0 <= shape < 6
     for t, b0 in zip(imgs, before):        # the tuner leaves u untouched
         assert torch.equal(t[0], b0)
     outs, _ = run_batched(probs, LAMS, p)
@@ -132,7 +133,8 @@ def test_batch64_workload_equals_per_image_runs():
     lams = [wl.lam] * len(probs)
     outs, st = run_batched(probs, lams, p)
     for i in range(0, len(probs), 7):
-        ref, _ = run_single(probs[i], wl.lam, wl.sigma, wl.tau, wl.n, M)
+        ref, _ = run_single(probs[i], wl.lam, wl.sigma, wl.tau, wl.n, M,
+                            flags=eed4.EED4_FORCE_SHAPE(4))
         assert np.array_equal(outs[i], ref)
     pr = probs[3]
     ref, _, _ = oracle.inpaint(pr["u_init"], pr["mask"], pr["known"], wl.lam, wl.sigma, wl.tau,

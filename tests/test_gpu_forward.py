@@ -20,7 +20,7 @@ if not torch.cuda.is_available():
 import paper_2006_10406_amd as eed4  # noqa: E402
 
 
-KERNELS = {"strip": 0, "tile": eed4.EED4_TILE_KERNEL}
+KERNELS = {"strip": eed4.EED4_FORCE_SHAPE(3), "tile": eed4.EED4_TILE_KERNEL}
 
 
 def gpu_cycle(states, mask, known, lam, sigma, tau, n, flags=0):
@@ -138,7 +138,7 @@ def test_equal_size_batch_matches_single_images():
     announce("equal-size batch vs single images")
     wl = WORKLOADS["adjoint16"]
     b = make_batch(wl, B=3, shape=(96, 80))
-    p = eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, 3)
+    p = eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, 3, flags=eed4.EED4_FORCE_SHAPE(3))
     u = to_dev(b["u_init"])
     eed4.eed4_inpaint(u, to_dev(b["mask"]), to_dev(b["known"]), p)
     batch = u.cpu().numpy()
@@ -173,7 +173,7 @@ def test_strip_and_tile_kernels_agree():
     announce("strip vs tile kernel, 300x260, 3 cycles")
     pr = make_problem(300, 260, 12, True, 0.01, 0.04, 555)
     outs = []
-    for f in (0, eed4.EED4_TILE_KERNEL):
+    for f in (eed4.EED4_FORCE_SHAPE(3), eed4.EED4_TILE_KERNEL):
         u = to_dev(pr["u_init"])
         eed4.eed4_inpaint(u, to_dev(pr["mask"]), to_dev(pr["known"]),
                           eed4.params(0.03, 1.5, 0.05, 15, 3, flags=f))
@@ -181,6 +181,26 @@ def test_strip_and_tile_kernels_agree():
     e = rel_l2(outs[0], outs[1])
     print(f"strip vs tile rel L2 {e:.3e}")
     assert e <= 1e-6
+
+
+@pytest.mark.parametrize("H,W,B", [(300, 260, 1), (96, 80, 4)])
+def test_every_step_shape_and_the_autotuned_default(H, W, B):
+    announce(f"all step shapes and the autotuned default, {B} x {H}x{W}")
+    b = {k: np.stack([make_problem(H, W, 8, True, 0.01, 0.05, 600 + i)[k] for i in range(B)])
+         for k in ("mask", "known", "u_init")}
+    outs = {}
+    for shape in list(range(6)) + [None]:
+        flags = 0 if shape is None else eed4.EED4_FORCE_SHAPE(shape)
+        u = to_dev(b["u_init"])
+        eed4.eed4_inpaint(u, to_dev(b["mask"]), to_dev(b["known"]),
+                          eed4.params(0.03, 1.5, 0.05, 9, 2, flags=flags))
+        outs[shape] = u.cpu().numpy()
+    for sh in (1, 2):
+        assert np.array_equal(outs[sh], outs[0])       # tile shapes: same arithmetic
+    for sh in (4, 5):
+        assert np.array_equal(outs[sh], outs[3])       # strip heights: same arithmetic
+    assert rel_l2(outs[3], outs[0]) <= 1e-6
+    assert np.array_equal(outs[None], outs[0]) or np.array_equal(outs[None], outs[3])
 
 
 def test_large4096_first_cycle_parity():

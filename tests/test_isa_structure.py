@@ -70,6 +70,9 @@ def _loops(asm, kernel):
 
 
 def test_tile_persistent_loops(tmp_path):
+    # one persistent loop per tile kernel, no atomics, and no loop nested in it
+    # that holds a barrier (such a loop is how a lane-dependent branch near the
+    # loop head once left waves spinning on a stale work index)
     asm = _assembly(tmp_path)
     kernels = [k for k in re.findall(r"^(_ZN4eed412btile_kernel\w+):", asm, re.M)]
     assert kernels
@@ -77,10 +80,7 @@ def test_tile_persistent_loops(tmp_path):
         loops, atom_blocks = _loops(asm, k)
         outer = [h for h, L in loops.items() if L["depth"] == 1]
         assert len(outer) == 1, (k, dict(loops))
-        # the pull sits in the persistent loop itself (its header or a block of it)
-        assert len(atom_blocks) == 1, (k, atom_blocks)
-        name, hdr = atom_blocks[0]
-        assert name == outer[0] or hdr == outer[0], (k, atom_blocks, outer)
+        assert not atom_blocks, (k, atom_blocks)
         nested_with_barrier = [h for h, L in loops.items() if L["depth"] > 1 and L["bar"]]
         assert not nested_with_barrier, (k, nested_with_barrier)
 
