@@ -15,7 +15,9 @@
  *
  * Conventions shared by every entry point
  *  - Images are row-major float32 [H][W] (x = column, fastest; y = row);
- *    a batch is [B][H][W] of equal-size images, contiguous.
+ *    a batch is [B][H][W] of equal-size images, contiguous.  Sizes:
+ *    1 <= H <= 2^24, 1 <= W <= 2^21, H*W <= 2^31, B*H*W <= 2^36; anything
+ *    else is EED4_EINVAL.
  *  - The mask is uint8 [B][H][W]; nonzero marks a known pixel.  known holds
  *    f and is read only where the mask is nonzero.
  *  - Every array pointer is a DEVICE pointer owned by the caller.  The library

@@ -29,7 +29,9 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 int check_params(const eed4_params *p, int B, int H, int W)
 {
     if (!p || B < 1 || H < 1 || W < 1) return EED4_EINVAL;
-    if (H > (1 << 24) || W > (1 << 24)) return EED4_EINVAL;
+    // W bound: a strip addresses up to 169 rows of one plane with a 32-bit
+    // byte offset that must stay below 2^31
+    if (H > (1 << 24) || W > (1 << 21)) return EED4_EINVAL;
     if ((long long)H * W > (1LL << 31) || (long long)B * H * W > (1LL << 36)) return EED4_EINVAL;
     if (!(p->lambda > 0.0f) || !std::isfinite(p->lambda)) return EED4_EINVAL;
     if (eed4_radius(p->sigma) < 0) return EED4_EINVAL;

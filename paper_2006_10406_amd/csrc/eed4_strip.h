@@ -83,13 +83,33 @@ struct StripArgs {
     float tau, alpha, il2q;     // il2q = 1 / (4 lambda^2)
 };
 
-// base + byte offset (a scalar row base plus a per-lane 32-bit offset)
-template <typename T>
-__device__ __forceinline__ T ldg(const T *base, unsigned byte_off)
+// Raw buffer resource over the `bytes` bytes from `base` (gfx9 descriptor:
+// stride 0, no swizzle).  A load at a byte offset at or beyond `bytes` reads 0
+// and a store there is dropped: lanes without an output pixel use kOffNone.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, unsigned bytes)
 {
-    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                             0x00020000);
+}
+constexpr unsigned kOffNone = 0x80000000u;
+
+__device__ __forceinline__ float buf_f32(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
 
+// Global loads of one stream row: u^k of the row itself, and u^{k-1}, the
+// mask and the residual reference of the output row it serves.
+struct StripRow {
+    float a, b, pv, rf;
+    unsigned mk;
+};
+
+// Addressing: every plane is seen through a buffer resource based at image
+// row b0 = max(Y0 - h, 0) (the lowest row a needed value comes from) and
+// covering nb = min(H - b0, NROW) rows, so a row offset is one 32-bit scalar
+// (the library keeps NROW * W * 4 below 2^31) and the per-lane column offsets
+// stay fixed for the whole strip.
 template <int R, bool RES, int ROWS = 64>
 __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
                                            const float (&w)[2 * kRMax + 1], double *partial)
@@ -98,17 +118,33 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
     constexpr int P = G::P, U = G::U, D = G::D, NU = G::NU;
     const int lane = threadIdx.x & 63;
     const int H = s.H, W = s.W;
+    const unsigned W4 = 4u * (unsigned)W;
 
-    // staged columns (fixed for the whole strip), as byte offsets into a row
+    const int ybase = s.Y0 - G::h;                            // image row of stream row 0
+    const int b0 = ybase > 0 ? ybase : 0;
+    const int nb = (H - b0 < G::NROW) ? H - b0 : G::NROW;
+    const size_t base = (size_t)b0 * W;
+    const __amdgpu_buffer_rsrc_t rs_u = buffer_rsrc(s.ucur + base, (unsigned)nb * W4);
+    const __amdgpu_buffer_rsrc_t rs_p = buffer_rsrc(s.uprev + base, (unsigned)nb * W4);
+    const __amdgpu_buffer_rsrc_t rs_o = buffer_rsrc(s.uout + base, (unsigned)nb * W4);
+    const __amdgpu_buffer_rsrc_t rs_m = buffer_rsrc(s.mask + base, (unsigned)nb * (unsigned)W);
+    __amdgpu_buffer_rsrc_t rs_r = rs_p;
+    if constexpr (RES) rs_r = buffer_rsrc(s.ref + base, (unsigned)nb * W4);
+
+    // staged columns (fixed for the whole strip): lane l stages column
+    // X0-2-R+l at ring position l, and the 2R right-halo columns X0+62-R..
+    // at positions 64..63+2R, lane l writing position 64 + l mod 2R (lanes
+    // with the same position load and write the same value)
     const unsigned ca = 4u * (unsigned)mirror_reflect(s.X0 - 2 - R + lane, W);
-    const bool has_b = lane < 2 * R;
-    const unsigned cb = has_b ? 4u * (unsigned)mirror_reflect(s.X0 + 62 - R + lane, W) : ca;
+    const int lb = R > 0 ? lane % (2 * R > 0 ? 2 * R : 1) : 0;
+    const unsigned cb = 4u * (unsigned)mirror_reflect(s.X0 + 62 - R + lb, W);
     const int cl = s.X0 - 2 + lane;                           // this lane's column
     const bool out_lane = lane >= 2 && lane < 62 && cl < W;
-    const unsigned co = out_lane ? (unsigned)cl : 0u;         // element offset in an output row
+    const unsigned vo4 = out_lane ? 4u * (unsigned)cl : kOffNone;
+    const unsigned vo1 = out_lane ? (unsigned)cl : kOffNone;
 
     float *rl = ring + lane;                                  // row r of the ring at r * NU
-    const int ybase = s.Y0 - G::h;                            // image row of stream row 0
+    float *rb = ring + 64 + lb;
 
     float win[P];             // x-pass values, row i in slot i % P
 #pragma unroll
@@ -119,34 +155,52 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
     float uc_p = 0.0f;                                   // u^k(g-1, c)
     double d2 = 0.0, n2 = 0.0;
 
-    // Global loads of a stream row are issued one row ahead, always in the
-    // same order (u^k row, then the output row's u^{k-1}, mask, reference),
-    // so waiting for one row never waits for the next row's loads.
-    float a_nx, b_nx, pv_nx = 0.0f, rf_nx = 0.0f;
-    unsigned mk_nx = 0;
-    auto prefetch = [&](int i) {
-        const int y = mirror_reflect(ybase + i, H);
-        const float *rowp = s.ucur + (size_t)y * W;
-        a_nx = ldg(rowp, ca);
-        b_nx = ldg(rowp, cb);
-        int o = ybase + i - R - 2;                       // output row served by row i
-        o = o < 0 ? 0 : (o >= H ? H - 1 : o);            // clamped; unused rows are not stored
-        const size_t ro = (size_t)o * W;
-        pv_nx = (s.uprev + ro)[co];
-        mk_nx = (s.mask + ro)[co];
-        if constexpr (RES) rf_nx = (s.ref + ro)[co];
+    // Row trackers of the next row to prefetch: its mirrored image row ym
+    // (moving in direction ydir; at an edge the row repeats and the direction
+    // flips, which is the half-sample mirror) and the output row it serves.
+    int ym = mirror_reflect(ybase, H);
+    int ydir;
+    {
+        const int k = ybase >= 0 ? ybase / H : -1 - (-1 - ybase) / H;   // mirror copy index
+        ydir = (k & 1) ? -1 : 1;
+    }
+    int on = ybase - R - 2;
+
+    // Loads run two stream rows ahead, always in the same order, so waiting
+    // for one row never waits for a later row's loads.
+    auto prefetch = [&](StripRow &r) {
+        const unsigned su = (unsigned)((ym > b0 ? ym : b0) - b0) * W4;
+        r.a = buf_f32(rs_u, ca, su);
+        if constexpr (R > 0) r.b = buf_f32(rs_u, cb, su);
+        int oc = on < b0 ? b0 : on;                      // clamped; unused rows are not stored
+        oc = oc > H - 1 ? H - 1 : oc;
+        const unsigned ro = (unsigned)(oc - b0);
+        r.pv = buf_f32(rs_p, vo4, ro * W4);
+        r.mk = __builtin_amdgcn_raw_buffer_load_b8(rs_m, vo1, ro * (unsigned)W, 0);
+        if constexpr (RES) r.rf = buf_f32(rs_r, vo4, ro * W4);
+        int nx = ym + ydir;
+        if ((unsigned)nx >= (unsigned)H) {
+            ydir = -ydir;
+            nx = ym;
+        }
+        ym = nx;
+        ++on;
     };
-    prefetch(0);
+    StripRow r0, r1;
+    r0.b = r1.b = r0.rf = r1.rf = 0.0f;
+    prefetch(r0);
+    prefetch(r1);
 
     // ---- prologue: stage rows 0 .. 2R-1 and their x pass ----
 #pragma unroll
     for (int i = 0; i < 2 * R; ++i) {
-        const float a = a_nx, b = b_nx;
-        prefetch(i + 1);
-        float *slot = rl + (i % D) * NU;
-        slot[0] = a;
-        if (has_b) slot[64] = b;
+        const float a = r0.a, b = r0.b;
+        r0 = r1;
+        prefetch(r1);
+        rl[(i % D) * NU] = a;
+        rb[(i % D) * NU] = b;
         wave_lds_sync();
+        const float *slot = rl + (i % D) * NU;
         float acc = w[0] * slot[0];
 #pragma unroll
         for (int j = 1; j <= 2 * R; ++j) acc = fmaf(w[j], slot[j], acc);
@@ -158,15 +212,16 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
 #pragma unroll
         for (int ph = 0; ph < U; ++ph) {
             const int i = 2 * R + it * U + ph;           // stream row (wave-uniform)
-            const float a = a_nx, b = b_nx, pv = pv_nx, rf = rf_nx;
-            const unsigned mk = mk_nx;
-            prefetch(i + 1);                              // mirrored: always valid rows
+            const StripRow cur = r0;
+            r0 = r1;
+            prefetch(r1);                                 // mirrored: always valid rows
 
             // ---- S1: stage u^k row i and take the x pass ----
-            float *slot = rl + ((2 * R + ph) % D) * NU;
-            slot[0] = a;
-            if (has_b) slot[64] = b;
+            const int sr = (2 * R + ph) % D;           // a constant once unrolled
+            rl[sr * NU] = cur.a;
+            if constexpr (R > 0) rb[sr * NU] = cur.b;
             wave_lds_sync();
+            const float *slot = rl + sr * NU;
             float acc = w[0] * slot[0];
 #pragma unroll
             for (int j = 1; j <= 2 * R; ++j) acc = fmaf(w[j], slot[j], acc);
@@ -187,8 +242,8 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
             const float *u0 = rl + ((R - 1 + ph + D) % D) * NU + R;    // row g
             const float *up = rl + ((R + ph) % D) * NU + R;            // row g + 1
             const float uc = u0[0];
-            const float hxx = (u0[-1] - uc) + (u0[1] - uc);
-            const float hyy = (um[0] - uc) + (up[0] - uc);
+            const float hxx = fmaf(-2.0f, uc, u0[-1] + u0[1]);
+            const float hyy = fmaf(-2.0f, uc, um[0] + up[0]);
             const float hxy = 0.25f * ((up[1] + um[-1]) - (up[-1] + um[1]));
 
             const float s2 = fmaf(gxs, gxs, gys * gys);                      // 4 |grad|^2
@@ -211,19 +266,21 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
             // ---- S4: output row o = g - 1 (stream row i - R - 2) ----
             const int o = ybase + i - R - 2;
             if (i >= 2 * G::h && o < H) {      // first output row of the segment is Y0
-                const float pu = ((from_prev_lane(txx_p) - txx_p) + (from_next_lane(txx_p) - txx_p)) +
-                                 ((tyy_pp - tyy_p) + (tyy - tyy_p)) + 0.5f * (z - z_pp);
-                if (out_lane) {
-                    const float wv = fmaf(-s.tau, pu, uc_p);
-                    float un = fmaf(s.alpha, wv - pv, pv);
-                    if (mk) un = uc_p;
-                    if constexpr (RES) {
-                        const double dd = (double)un - (double)rf;
-                        d2 = fma(dd, dd, d2);
-                        n2 = fma((double)un, (double)un, n2);
-                    }
-                    (s.uout + (size_t)o * W)[co] = un;
+                const float sxx = from_prev_lane(txx_p) + from_next_lane(txx_p);
+                const float pu = fmaf(-2.0f, txx_p + tyy_p, sxx + (tyy_pp + tyy)) +
+                                 0.5f * (z - z_pp);
+                const float wv = fmaf(-s.tau, pu, uc_p);
+                float un = fmaf(s.alpha, wv - cur.pv, cur.pv);
+                if (cur.mk) un = uc_p;
+                if constexpr (RES) {
+                    // lanes without a pixel read 0 for the reference; add 0
+                    const double du = out_lane ? (double)un : 0.0;
+                    const double dd = du - (double)cur.rf;
+                    d2 = fma(dd, dd, d2);
+                    n2 = fma(du, du, n2);
                 }
+                const unsigned ro = (unsigned)(o - b0);
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(un), rs_o, vo4, ro * W4, 0);
             }
             tyy_pp = tyy_p;
             tyy_p = tyy;

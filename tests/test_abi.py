@@ -79,6 +79,8 @@ def test_argument_errors_before_any_gpu_work(lib):
     assert _call_inpaint(lib, e.params(0.05, 1.0, -0.01, 10, 2)) == e._lib.EED4_EINVAL
     assert _call_inpaint(lib, e.params(0.05, 1.0, 0.05, 10, 2, tol=-1.0)) == e._lib.EED4_EINVAL
     assert _call_inpaint(lib, ok, H=0) == e._lib.EED4_EINVAL
+    assert _call_inpaint(lib, ok, H=1, W=(1 << 21) + 1) == e._lib.EED4_EINVAL   # width bound
+    assert _call_inpaint(lib, ok, H=(1 << 24) + 1, W=1) == e._lib.EED4_EINVAL
     assert _call_inpaint(lib, ok, ptr=0) == e._lib.EED4_EINVAL
     assert _call_inpaint(lib, ok, ws=0) == e._lib.EED4_EWORKSPACE
     assert _call_inpaint(lib, ok, ws=0x1001) == e._lib.EED4_EWORKSPACE
