@@ -75,7 +75,8 @@ extern "C" {
 /* Use kernel shape s for the fused step instead of the automatic choice
  * (the autotuner in eed4_inpaint_batched, a work-size rule elsewhere):
  * 0: 64x32 workgroup tiles, 1: 64x16 tiles, 2: 32x32 tiles, 3: wave strips of
- * 60 columns x >= 64 rows, 4: strips of >= 136 rows, 5: strips of >= 28 rows.
+ * 60 columns x >= 64 rows, 4: strips of >= 136 rows, 5: strips of >= 28 rows,
+ * 6: strips of >= 8 rows.
  * All strip heights give bitwise the same results; so do all tile shapes. */
 #define EED4_FORCE_SHAPE(s)  ((((s) + 1) & 0xff) << 8)
 

@@ -25,7 +25,8 @@ def EED4_FORCE_SHAPE(s):
     return ((s + 1) & 0xFF) << 8
 
 
-SHAPE_NAMES = ("tile64x32", "tile64x16", "tile32x32", "strip", "strip_tall", "strip_short")
+SHAPE_NAMES = ("tile64x32", "tile64x16", "tile32x32", "strip", "strip_tall", "strip_short",
+               "strip_tiny")
 
 EED4_OP_INPAINT = 1
 EED4_OP_CYCLE = 2

@@ -5,13 +5,17 @@
 // the actual batch.
 //
 // The queue holds one entry per work item (a tile of a workgroup, or a strip
-// segment of a wave) of every image still iterating.  A launch keeps a fixed
-// set of resident workgroups that walk the queue with a static stride; every
-// XCD takes contiguous runs of items, so neighbouring items share its L2.  (A
+// segment of a wave) of every image still iterating.  A launch has one wave or
+// workgroup per item of the full queue and walks the queue with a static
+// stride (a no-op loop unless the grid is smaller than the queue); every XCD
+// takes contiguous runs of items, so neighbouring items share its L2.  (A
 // global atomic work counter was tried first: with one device-scope counter
-// for all XCDs the pulls serialise and the step took twice as long.)  The
-// queue length lives in device memory: dropping a converged image rewrites the
-// queue without re-capturing the graph.
+// for all XCDs the pulls serialise and the step took twice as long.  A grid
+// capped at the resident capacity was tried next: where the kernel's occupancy
+// left fewer wave slots than items, some waves took a second item after the
+// others had finished, which cost a third on the 64-image batch.)  The queue
+// length lives in device memory: dropping a converged image rewrites the queue
+// without re-capturing the graph; waves past its end exit at once.
 #include "eed4.h"
 #include "eed4_host.h"
 #include "eed4_internal.h"
@@ -23,8 +27,6 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
-#include <map>
-#include <mutex>
 #include <string>
 #include <vector>
 
@@ -47,6 +49,20 @@ __device__ __forceinline__ float *pick(const BImage &d, int sel)
     return sel == 0 ? d.buf[0] : (sel == 1 ? d.buf[1] : d.buf[2]);
 }
 
+// Wave-uniform copies of values loaded from the queue and the descriptors.
+// The loads use a uniform address, but their results land in VGPRs; buffer
+// resources built from them would make the compiler wrap every buffer access
+// in a loop over distinct lane values.
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+template <typename T>
+__device__ __forceinline__ T *uni(T *p)
+{
+    const unsigned long long v = (unsigned long long)p;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return (T *)(((unsigned long long)hi << 32) | lo);
+}
+
 // Wave-strip shapes: wave w of the launch takes items w, w + nw, w + 2 nw, ...
 // (w counted in XCD-contiguous order).
 template <int R, int ROWS, bool RES>
@@ -64,19 +80,19 @@ __global__ __launch_bounds__(256) void bstrip_kernel(const BImage *imgs, const B
         const BItem t = queue[it];
         const BImage d = imgs[t.img];
         StripArgs s;
-        s.ucur = pick(d, sc);
-        s.uprev = pick(d, sp);
-        s.uout = pick(d, so);
-        s.ref = d.buf[0];
-        s.mask = d.mask;
-        s.H = d.H;
-        s.W = d.W;
-        s.X0 = t.ix * G::SW;
-        s.Y0 = t.iy * G::OH;
+        s.ucur = uni(pick(d, sc));
+        s.uprev = uni(pick(d, sp));
+        s.uout = uni(pick(d, so));
+        s.ref = uni(d.buf[0]);
+        s.mask = uni(d.mask);
+        s.H = uni(d.H);
+        s.W = uni(d.W);
+        s.X0 = uni(t.ix) * G::SW;
+        s.Y0 = uni(t.iy) * G::OH;
         s.tau = a.tau;
         s.alpha = a.alpha;
-        s.il2q = 0.25f * d.inv_lam2;
-        strip_step<R, RES, ROWS>(lds + wave * G::LDS, s, a.w, partials + 2 * (size_t)t.slot);
+        s.il2q = 0.25f * __int_as_float(uni(__float_as_int(d.inv_lam2)));
+        strip_step<R, RES, ROWS>(lds + wave * G::LDS, s, a.w, partials + 2 * (size_t)uni(t.slot));
     }
 }
 
@@ -92,10 +108,11 @@ __global__ __launch_bounds__(256) void btile_kernel(const BImage *imgs, const BI
         __syncthreads();           // the previous tile's last LDS reads are done
         const BItem t = queue[it];
         const BImage d = imgs[t.img];
-        step_tile<R, TW, TH>(smem, pick(d, sc), pick(d, sp), pick(d, so),
-                             residual ? d.buf[0] : nullptr, d.mask, d.H, d.W, t.iy, t.ix, a.w,
-                             a.tau, a.alpha, d.inv_lam2,
-                             residual ? partials + 2 * (size_t)t.slot : nullptr);
+        step_tile<R, TW, TH>(smem, uni(pick(d, sc)), uni(pick(d, sp)), uni(pick(d, so)),
+                             residual ? uni(d.buf[0]) : nullptr, uni(d.mask), uni(d.H), uni(d.W),
+                             uni(t.iy), uni(t.ix), a.w, a.tau, a.alpha,
+                             __int_as_float(uni(__float_as_int(d.inv_lam2))),
+                             residual ? partials + 2 * (size_t)uni(t.slot) : nullptr);
     }
 }
 
@@ -192,6 +209,7 @@ static hipError_t launch_bstep_r(int shape, int grid, const BImage *imgs, const 
     case kShapeStrip: EED4_BSTRIP(64); break;
     case kShapeStripTall: EED4_BSTRIP(136); break;
     case kShapeStripShort: EED4_BSTRIP(28); break;
+    case kShapeStripTiny: EED4_BSTRIP(8); break;
     default: return hipErrorInvalidValue;
     }
 #undef EED4_BTILE
@@ -211,44 +229,6 @@ static hipError_t launch_bstep(int R, int shape, int grid, const BImage *imgs, c
 #undef EED4_CASE
     default: return hipErrorInvalidValue;
     }
-}
-
-// Persistent grid: enough workgroups to fill every CU at the kernel's occupancy.
-static int persistent_grid(int R, int shape)
-{
-    static std::mutex mu;
-    static std::map<std::pair<int, int>, int> cache;
-    std::lock_guard<std::mutex> lk(mu);
-    auto key = std::make_pair(R, shape);
-    auto f = cache.find(key);
-    if (f != cache.end()) return f->second;
-    int dev = 0, cus = 256, per = 4;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const void *fn = nullptr;
-    switch (shape * 16 + R) {
-#define EED4_FN(sh, r, K) case sh * 16 + r: fn = (const void *)(K); break;
-#define EED4_FNS(r)                                                     \
-    EED4_FN(0, r, (btile_kernel<r, 64, 32>))                            \
-    EED4_FN(1, r, (btile_kernel<r, 64, 16>))                            \
-    EED4_FN(2, r, (btile_kernel<r, 32, 32>))                            \
-    EED4_FN(3, r, (bstrip_kernel<r, 64, false>))                        \
-    EED4_FN(4, r, (bstrip_kernel<r, 136, false>))                       \
-    EED4_FN(5, r, (bstrip_kernel<r, 28, false>))
-        EED4_FNS(0) EED4_FNS(1) EED4_FNS(2) EED4_FNS(3) EED4_FNS(4)
-        EED4_FNS(5) EED4_FNS(6) EED4_FNS(7) EED4_FNS(8)
-#undef EED4_FNS
-#undef EED4_FN
-    default: break;
-    }
-    if (fn) {
-        int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, 0) == hipSuccess && nb > 0)
-            per = nb;
-    }
-    int g = cus * per;
-    cache[key] = g;
-    return g;
 }
 
 struct BatchLayout {
@@ -348,7 +328,6 @@ static int prepare(BatchRun &r, const eed4_image *im, int B, const eed4_params *
     r.B = B;
     r.p = p;
     item_dims(shape, r.R, &r.iw, &r.ih);
-    r.grid = persistent_grid(r.R, shape);
     r.himg.resize(B);
     r.slot0.resize(B);
     r.nslot.resize(B);
@@ -384,10 +363,11 @@ static int prepare(BatchRun &r, const eed4_image *im, int B, const eed4_params *
     if (e != hipSuccess) return hip_fail(e, "descriptor upload");
     std::vector<char> active(B, 1);
     build_queue(r, active);
-    // resident workgroups: no more than the work (4 strip items per workgroup)
+    // one wave (strip) or workgroup (tile) per item of the full queue; the
+    // hardware dispatcher balances them.  Later cycles may have fewer items:
+    // the waves past the queue length exit at once.
     const int ql = (int)r.queue.size();
-    const int need = is_strip(shape) ? (ql + 3) / 4 : ql;
-    r.grid = std::max(1, std::min(r.grid, need));
+    r.grid = std::max(1, is_strip(shape) ? (ql + 3) / 4 : ql);
     return upload_queue(r, s);
 }
 

@@ -112,6 +112,7 @@ static int strip_oh(int shape)
     switch (shape) {
     case kShapeStripTall: return StripGeo<R, 136>::OH;
     case kShapeStripShort: return StripGeo<R, 28>::OH;
+    case kShapeStripTiny: return StripGeo<R, 8>::OH;
     default: return StripGeo<R, 64>::OH;
     }
 }
@@ -184,6 +185,7 @@ static hipError_t launch_step_r(int shape, const float *ucur, const float *uprev
     case kShapeStrip: return launch_strip_t<R, 64>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
     case kShapeStripTall: return launch_strip_t<R, 136>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
     case kShapeStripShort: return launch_strip_t<R, 28>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
+    case kShapeStripTiny: return launch_strip_t<R, 8>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -25,18 +25,22 @@ struct TileShape {
 };
 
 // Kernel shapes compiled into the library (index = config id): 0..2 are
-// workgroup tiles (tw x th outputs per 256-thread workgroup); 3 is the
-// wave-strip kernel (60 columns x a radius-dependent row count per wave).
+// workgroup tiles (tw x th outputs per 256-thread workgroup); 3..6 are
+// wave strips (60 columns x a segment of rows per wave).
 constexpr int kNumTileShapes = 3;
 constexpr TileShape kTileShapes[kNumTileShapes] = {{64, 32}, {64, 16}, {32, 32}};
 constexpr int kShapeStrip = 3;       // wave strips of >= 64 output rows
 constexpr int kShapeStripTall = 4;   // >= 136 rows
 constexpr int kShapeStripShort = 5;  // >= 28 rows (more waves for small images)
-constexpr int kNumShapes = 6;
+constexpr int kShapeStripTiny = 6;   // >= 8 rows (shortest row pipeline per wave)
+constexpr int kNumShapes = 7;
 constexpr bool is_strip(int shape) { return shape >= kShapeStrip && shape < kNumShapes; }
 constexpr int strip_target_rows(int shape)
 {
-    return shape == kShapeStripTall ? 136 : (shape == kShapeStripShort ? 28 : 64);
+    return shape == kShapeStripTall ? 136
+         : shape == kShapeStripShort ? 28
+         : shape == kShapeStripTiny  ? 8
+                                     : 64;
 }
 
 // Device-side descriptor of one image of an uneven batch.

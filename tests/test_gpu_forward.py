@@ -189,7 +189,7 @@ def test_every_step_shape_and_the_autotuned_default(H, W, B):
     b = {k: np.stack([make_problem(H, W, 8, True, 0.01, 0.05, 600 + i)[k] for i in range(B)])
          for k in ("mask", "known", "u_init")}
     outs = {}
-    for shape in list(range(6)) + [None]:
+    for shape in list(range(len(eed4.SHAPE_NAMES))) + [None]:
         flags = 0 if shape is None else eed4.EED4_FORCE_SHAPE(shape)
         u = to_dev(b["u_init"])
         eed4.eed4_inpaint(u, to_dev(b["mask"]), to_dev(b["known"]),
@@ -197,7 +197,7 @@ def test_every_step_shape_and_the_autotuned_default(H, W, B):
         outs[shape] = u.cpu().numpy()
     for sh in (1, 2):
         assert np.array_equal(outs[sh], outs[0])       # tile shapes: same arithmetic
-    for sh in (4, 5):
+    for sh in range(4, len(eed4.SHAPE_NAMES)):
         assert np.array_equal(outs[sh], outs[3])       # strip heights: same arithmetic
     assert rel_l2(outs[3], outs[0]) <= 1e-6
     assert np.array_equal(outs[None], outs[0]) or np.array_equal(outs[None], outs[3])
