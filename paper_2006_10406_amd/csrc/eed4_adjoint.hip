@@ -12,13 +12,24 @@
 //   lambdabar  += -alpha_k tau <dF/dlambda, r>
 // with J_F(u)^T r = P(u) r + C^T q, C = (grad of the presmoothed image) and
 // q_p = de_p/dG_p for e_p = (B r)_p : D(G_p) : (B u)_p (B = Hessian).
-// Pass A computes P(u) r, q and de/dlambda; pass B applies
-// C^T q = K_sigma (-div q) and the pointwise update.  Both evaluate on the
-// mirror-extended image: q_x is odd across vertical borders and even across
-// horizontal ones, q_y the reverse, which makes every transpose exact.
+// Everything is evaluated on the mirror-extended image, which makes every
+// transpose exact: q_x comes out odd across vertical borders and even across
+// horizontal ones, q_y the reverse.
+//
+// Two implementations of a reverse step:
+//  - workgroup tiles: pass A computes P(u) r, q and de/dlambda into global
+//    buffers; pass B applies C^T q = K_sigma (-div q) and the update;
+//  - wave strips (one launch): a wave streams down a strip and carries every
+//    intermediate in registers and a per-wave LDS ring, as the forward strip
+//    kernel does.
+// Known pixels: r is 0 there, so ubar on a known pixel feeds nothing but fbar.
+// Both implementations therefore keep on known pixels the running sum of ubar
+// over the reverse steps done so far; fbar is that sum at the end.  lambdabar
+// is accumulated per work item across all reverse steps and reduced once.
 #include "eed4.h"
 #include "eed4_host.h"
 #include "eed4_internal.h"
+#include "eed4_strip.h"
 #include "eed4_tile.h"
 
 #include <cmath>
@@ -33,7 +44,7 @@ constexpr int kAdjTW = 64, kAdjTH = 16;
 // e = A : D(G) : H.  In the gradient frame n = G/|G|, t = n rotated by +90
 // degrees, e = A:H + (mu1 - 1) a1 h1 + 2 (mu3 - 1) a3 h3 with a1 = n.A.n,
 // a3 = t.A.n; d/ds and d/dtheta of it give q = (de/ds) n + (1/s)(de/dtheta) t.
-__device__ __forceinline__ void adjoint_point(float gx, float gy, float lam, float inv_lam2,
+__device__ __forceinline__ void adjoint_point(float gx, float gy, float inv_lam2, float inv_lam3,
                                               float axx, float ayy, float axy, float hxx,
                                               float hyy, float hxy, float &txx, float &tyy,
                                               float &txy, float &qx, float &qy, float &dl)
@@ -63,7 +74,7 @@ __device__ __forceinline__ void adjoint_point(float gx, float gy, float lam, flo
     const float m12 = mu1 * mu1;
     const float X = fmaf(m12 * mu1, a1 * h1, m12 * mu3 * (a3 * h3));
     const float de_ds = -s * inv_lam2 * X;
-    dl = (s2 * inv_lam2 / lam) * X;
+    dl = (s2 * inv_lam3) * X;
     // (mu1 - 1)/s = -s mu1^2 / (lam^2 (1 + mu1)), (mu3 - 1)/s = that / (1 + mu3)
     const float rp = __builtin_amdgcn_rcpf((1.0f + mu1) * (1.0f + mu3));
     const float p1 = fmaf(a3, h1, a1 * h3);
@@ -71,6 +82,22 @@ __device__ __forceinline__ void adjoint_point(float gx, float gy, float lam, flo
     const float dth = -2.0f * s * m12 * inv_lam2 * rp * fmaf(p1, 1.0f + mu3, p2);
     qx = fmaf(nx, de_ds, -ny * dth);
     qy = fmaf(ny, de_ds, nx * dth);
+}
+
+// acc[0] += the workgroup's sum of v (fixed order; the same workgroup index
+// owns the same slot in every launch, so the running sums are deterministic).
+__device__ __forceinline__ void block_accumulate(double v, double *scratch, double *acc)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) scratch[wv] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < kThreads / 64; ++i) t += scratch[i];
+        acc[0] += t;
+    }
 }
 
 template <int R>
@@ -92,7 +119,7 @@ template <int R>
 __global__ __launch_bounds__(256) void adjoint_a_kernel(const float *u_all, const float *an_all,
                                                         const uint8_t *__restrict__ mask_all,
                                                         int H, int W, int nbx, int tiles_per_img,
-                                                        StepArgs a, float lam, float lam_scale,
+                                                        StepArgs a, float il3, float lam_scale,
                                                         float *qx_all, float *qy_all,
                                                         float *pr_all, double *lam_partials)
 {
@@ -164,7 +191,7 @@ __global__ __launch_bounds__(256) void adjoint_a_kernel(const float *u_all, cons
             float ayy = (rr[-G::RW] - rc) + (rr[G::RW] - rc);
             float axy = 0.25f * ((rr[G::RW + 1] + rr[-G::RW - 1]) - (rr[G::RW - 1] + rr[-G::RW + 1]));
             float qx, qy, dl;
-            adjoint_point(gx, gy, lam, a.inv_lam2, axx, ayy, axy, hxx, hyy, hxy, txx[k], tyy[k],
+            adjoint_point(gx, gy, a.inv_lam2, il3, axx, ayy, axy, hxx, hyy, hxy, txx[k], tyy[k],
                           txy[k], qx, qy, dl);
             int yy = gy0 + pr - 1, xx = gx0 + pc - 1;
             if (pr >= 1 && pr <= TH && pc >= 1 && pc <= TW && yy < H && xx < W) {
@@ -200,8 +227,8 @@ __global__ __launch_bounds__(256) void adjoint_a_kernel(const float *u_all, cons
         }
     }
     __syncthreads();
-    block_sum2(dlsum * (double)lam_scale, 0.0, reinterpret_cast<double *>(smem),
-               lam_partials + 2 * (size_t)tile);
+    block_accumulate(dlsum * (double)lam_scale, reinterpret_cast<double *>(smem),
+                     lam_partials + 2 * (size_t)tile);
 }
 
 template <int R>
@@ -230,10 +257,10 @@ __device__ __forceinline__ float load_q(const float *q, int y, int x, int H, int
 // Pass B on one 64 x 16 tile: C^T q and the pointwise reverse-step update.
 template <int R>
 __global__ __launch_bounds__(256) void adjoint_b_kernel(const float *qx_all, const float *qy_all,
-                                                        const float *pr_all, float *an_all,
-                                                        float *ac_all,
+                                                        const float *pr_all, const float *an_all,
+                                                        float *ac_all, float *ap_all,
                                                         const uint8_t *__restrict__ mask_all,
-                                                        float *gk_all, int H, int W, int nbx,
+                                                        int H, int W, int nbx,
                                                         int tiles_per_img, StepArgs a, int first)
 {
     using G = AdjBGeo<R>;
@@ -284,10 +311,290 @@ __global__ __launch_bounds__(256) void adjoint_b_kernel(const float *qx_all, con
         float acv = fmaf(a.alpha, fmaf(-a.tau, z, rv), ac_all[gi]);
         const float back = (1.0f - a.alpha) * rv;
         if (first) acv += back;
+        else ap_all[gi] = back;
+        if (m) acv += anv;              // known pixel: running sum of ubar
         ac_all[gi] = acv;
-        if (!first) an_all[gi] = back;
-        if (m) gk_all[gi] += anv;
     }
+}
+
+// ---- fused reverse step on wave strips ----
+//
+// A wave owns 64 consecutive columns c = X0-2-R .. X0+61-R (one per lane) and
+// streams down the rows of a segment.  For each stream row i it
+//   S1  stages u^k(i) in a per-wave LDS ring and takes the x pass of the
+//       presmoothing;
+//   S2  completes the y pass at row i-R;
+//   S3  at row g = i-R-1: gradient of u_sigma, Hessian of u (ring), Hessian of
+//       r = mbar ubar^{k+1} (r rows in registers, lane neighbours by DPP), and
+//       the adjoint point quantities D:A, q, de/dlambda;
+//   S4  at row g-1: P(u) r from the outer differences of D:A, and
+//       d = -div q, whose x pass goes through a one-row LDS buffer into a
+//       register window;
+//   S5  at row o = i-2R-2: y pass of d (C^T q) and the reverse update.
+// Lanes R+2 .. 61-R own output columns (60-2R per wave).  The input halo is
+// 2R+2 rows each way.
+template <int R, int ROWS>
+struct AdjStripGeo {
+    static constexpr int P = 2 * R + 1;                       // window length
+    static constexpr int U = P * ((R + 3 + P - 1) / P);       // unroll = LDS ring depth
+    static constexpr int D = U;
+    static constexpr int h = 2 * R + 2;                       // input row halo
+    static constexpr int hc = R + 2;                          // first output lane
+    static constexpr int SW = 64 - 2 * hc;                    // output columns per wave
+    static constexpr int NU = 64 + 2 * R;                     // staged u columns per row
+    static constexpr int ND = 64 + 2 * R;                     // d row, R pad on each side
+    static constexpr int M = (ROWS + 2 * h - 2 * R + U - 1) / U;
+    static constexpr int NROW = 2 * R + M * U;                // rows streamed per wave
+    static constexpr int OH = NROW - 2 * h;                   // output rows per wave
+    static constexpr int LDS = D * NU + ND;                   // floats of LDS per wave
+};
+
+struct AdjStripArgs {
+    const float *u, *an;        // u^k, ubar^{k+1}
+    float *ac, *ap;             // ubar^k (accumulated in place), ubar^{k-1} contribution
+    const uint8_t *mask;
+    int H, W, X0, Y0;
+    float tau, alpha, il2, il3; // il2 = 1/lambda^2, il3 = 1/lambda^3
+    int first;                  // k == 0: the (1-alpha) r term goes to ubar^k itself
+};
+
+// Global loads of one stream row: u^k of the row, r of the row R above it,
+// and ubar^{k+1}, ubar^k and the mask of the output row it serves.
+struct AdjStripRow {
+    float a, b, rn, oa, oc;
+    unsigned rmk, omk;
+};
+
+template <int R, int ROWS>
+__device__ __forceinline__ void adjoint_strip_step(float *ring, const AdjStripArgs &s,
+                                                   const float (&w)[2 * kRMax + 1],
+                                                   double *partial, float lam_scale)
+{
+    using G = AdjStripGeo<R, ROWS>;
+    constexpr int P = G::P, U = G::U, D = G::D, NU = G::NU, h = G::h;
+    const int lane = threadIdx.x & 63;
+    const int H = s.H, W = s.W;
+    const unsigned W4 = 4u * (unsigned)W;
+
+    // resources based at the lowest row a needed value comes from (as in
+    // the forward strip)
+    const int ybase = s.Y0 - h;                               // image row of stream row 0
+    const int b0 = ybase > 0 ? ybase : 0;
+    const int nb = (H - b0 < G::NROW) ? H - b0 : G::NROW;
+    const size_t base = (size_t)b0 * W;
+    const __amdgpu_buffer_rsrc_t rs_u = buffer_rsrc(s.u + base, (unsigned)nb * W4);
+    const __amdgpu_buffer_rsrc_t rs_an = buffer_rsrc(s.an + base, (unsigned)nb * W4);
+    const __amdgpu_buffer_rsrc_t rs_ac = buffer_rsrc(s.ac + base, (unsigned)nb * W4);
+    const __amdgpu_buffer_rsrc_t rs_ap = buffer_rsrc(s.ap + base, (unsigned)nb * W4);
+    const __amdgpu_buffer_rsrc_t rs_m = buffer_rsrc(s.mask + base, (unsigned)nb * (unsigned)W);
+
+    const int c0 = s.X0 - G::hc;                              // column of lane 0
+    const unsigned ca = 4u * (unsigned)mirror_reflect(c0 - R + lane, W);
+    const int lb = R > 0 ? lane % (2 * R > 0 ? 2 * R : 1) : 0;
+    const unsigned cb = 4u * (unsigned)mirror_reflect(c0 - R + 64 + lb, W);
+    const int cl = c0 + lane;                                 // this lane's column
+    const unsigned cm = (unsigned)mirror_reflect(cl, W);      // ... mirrored into the image
+    const bool out_lane = lane >= G::hc && lane < 64 - G::hc && cl < W;
+    const unsigned vo4 = out_lane ? 4u * (unsigned)cl : kOffNone;
+    const unsigned vo1 = out_lane ? (unsigned)cl : kOffNone;
+    const int yend = s.Y0 + G::OH < H ? s.Y0 + G::OH : H;     // rows owned: [Y0, yend)
+
+    float *rl = ring + lane;                                  // u ring row r at r * NU
+    float *rb = ring + 64 + lb;
+    float *dw = ring + D * NU + lane;                         // d row: lane l at l + R
+
+    float win[P], dwin[P], prw[P];    // x-pass u, x-pass d, P(u) r; row j in slot j % P
+#pragma unroll
+    for (int j = 0; j < P; ++j) win[j] = dwin[j] = prw[j] = 0.0f;
+    float v_m1 = 0.0f, v_m2 = 0.0f;                          // v at rows g, g-1 (before update)
+    float r_m1 = 0.0f, r_0 = 0.0f;                           // r at rows g-1, g
+    float txx_p = 0.0f, tyy_p = 0.0f, tyy_pp = 0.0f;         // D:A at rows g-1 (g-2 for yy)
+    float z_p = 0.0f, z_pp = 0.0f;                           // (D:A)xy(l+1)-(D:A)xy(l-1)
+    float qx_p = 0.0f, qy_p = 0.0f, qy_pp = 0.0f;            // q at rows g-1 (g-2 for y)
+    double dsum = 0.0;
+
+    RowTrack tu, tr;                  // next prefetch: u row, r row (R rows behind)
+    tu.init(ybase, H);
+    tr.init(ybase - R, H);
+    int on = ybase - h;                                       // output row it serves
+    auto prefetch = [&](AdjStripRow &r) {
+        const unsigned su = (unsigned)((tu.y > b0 ? tu.y : b0) - b0) * W4;
+        r.a = buf_f32(rs_u, ca, su);
+        if constexpr (R > 0) r.b = buf_f32(rs_u, cb, su);
+        const unsigned sr = (unsigned)((tr.y > b0 ? tr.y : b0) - b0);
+        r.rn = buf_f32(rs_an, 4u * cm, sr * W4);
+        r.rmk = __builtin_amdgcn_raw_buffer_load_b8(rs_m, cm, sr * (unsigned)W, 0);
+        int oc = on < b0 ? b0 : on;                           // clamped; unused rows are not stored
+        oc = oc > H - 1 ? H - 1 : oc;
+        const unsigned ro = (unsigned)(oc - b0);
+        r.oa = buf_f32(rs_an, vo4, ro * W4);
+        r.oc = buf_f32(rs_ac, vo4, ro * W4);
+        r.omk = __builtin_amdgcn_raw_buffer_load_b8(rs_m, vo1, ro * (unsigned)W, 0);
+        tu.next(H);
+        tr.next(H);
+        ++on;
+    };
+    AdjStripRow r0, r1;
+    r0.b = r1.b = 0.0f;
+    prefetch(r0);
+    prefetch(r1);
+
+    // ---- prologue: stream rows 0 .. 2R-1 (x pass; r rows roll through) ----
+#pragma unroll
+    for (int i = 0; i < 2 * R; ++i) {
+        const AdjStripRow cur = r0;
+        r0 = r1;
+        prefetch(r1);
+        rl[(i % D) * NU] = cur.a;
+        rb[(i % D) * NU] = cur.b;
+        wave_lds_sync();
+        const float *slot = rl + (i % D) * NU;
+        float acc = w[0] * slot[0];
+#pragma unroll
+        for (int j = 1; j <= 2 * R; ++j) acc = fmaf(w[j], slot[j], acc);
+        win[i % P] = acc;
+        r_m1 = r_0;
+        r_0 = cur.rmk ? 0.0f : cur.rn;
+    }
+
+#pragma unroll 1
+    for (int it = 0; it < G::M; ++it) {
+#pragma unroll
+        for (int ph = 0; ph < U; ++ph) {
+            const int i = 2 * R + it * U + ph;               // stream row (wave-uniform)
+            const AdjStripRow cur = r0;
+            r0 = r1;
+            prefetch(r1);
+
+            // ---- S1: stage u^k row i, x pass ----
+            const int sr = (2 * R + ph) % D;                 // constants once unrolled
+            rl[sr * NU] = cur.a;
+            if constexpr (R > 0) rb[sr * NU] = cur.b;
+            wave_lds_sync();
+            const float *slot = rl + sr * NU;
+            float acc = w[0] * slot[0];
+#pragma unroll
+            for (int j = 1; j <= 2 * R; ++j) acc = fmaf(w[j], slot[j], acc);
+            win[(2 * R + ph) % P] = acc;
+
+            // ---- S2: y pass at stream row i - R ----
+            float v = w[0] * win[ph % P];
+#pragma unroll
+            for (int j = 1; j <= 2 * R; ++j) v = fmaf(w[j], win[(ph + j) % P], v);
+
+            // ---- S3 at row g = i - R - 1 ----
+            const float gxs = from_next_lane(v_m1) - from_prev_lane(v_m1);  // 2 gx
+            const float gys = v - v_m2;                                      // 2 gy
+            v_m2 = v_m1;
+            v_m1 = v;
+            const float *um = rl + ((R - 2 + ph + D) % D) * NU + R;    // row g - 1
+            const float *u0 = rl + ((R - 1 + ph + D) % D) * NU + R;    // row g
+            const float *up = rl + ((R + ph) % D) * NU + R;            // row g + 1
+            const float uc = u0[0];
+            const float hxx = fmaf(-2.0f, uc, u0[-1] + u0[1]);
+            const float hyy = fmaf(-2.0f, uc, um[0] + up[0]);
+            const float hxy = 0.25f * ((up[1] + um[-1]) - (up[-1] + um[1]));
+            const float r_p1 = cur.rmk ? 0.0f : cur.rn;                // r at row g + 1
+            const float axx = fmaf(-2.0f, r_0, from_prev_lane(r_0) + from_next_lane(r_0));
+            const float ayy = fmaf(-2.0f, r_0, r_m1 + r_p1);
+            const float axy = 0.25f * ((from_next_lane(r_p1) - from_prev_lane(r_p1)) -
+                                       (from_next_lane(r_m1) - from_prev_lane(r_m1)));
+            r_m1 = r_0;
+            r_0 = r_p1;
+            float tx, ty, txy, qx, qy, dl;
+            adjoint_point(0.5f * gxs, 0.5f * gys, s.il2, s.il3, axx, ayy, axy, hxx, hyy, hxy, tx,
+                          ty, txy, qx, qy, dl);
+            const int g = ybase + i - R - 1;                          // image row of S3
+            dsum += (g >= s.Y0 && g < yend && out_lane) ? (double)dl : 0.0;
+            const float z = from_next_lane(txy) - from_prev_lane(txy);
+
+            // ---- S4 at row g - 1: P(u) r and d = -div q ----
+            const float sxx = from_prev_lane(txx_p) + from_next_lane(txx_p);
+            const float pr = fmaf(-2.0f, txx_p + tyy_p, sxx + (tyy_pp + ty)) + 0.5f * (z - z_pp);
+            const float d = -0.5f * ((from_next_lane(qx_p) - from_prev_lane(qx_p)) + (qy - qy_pp));
+            dw[R] = d;
+            wave_lds_sync();
+            float dx = w[0] * dw[0];
+#pragma unroll
+            for (int j = 1; j <= 2 * R; ++j) dx = fmaf(w[j], dw[j], dx);
+            constexpr int kP = P;                                     // slot of row i - R - 2
+            const int jd = ((R - 2 + ph) % kP + kP) % kP;
+            dwin[jd] = dx;
+            prw[jd] = pr;
+            tyy_pp = tyy_p;
+            tyy_p = ty;
+            txx_p = tx;
+            z_pp = z_p;
+            z_p = z;
+            qy_pp = qy_p;
+            qy_p = qy;
+            qx_p = qx;
+
+            // ---- S5: output row o (stream row i - 2R - 2) ----
+            const int o = ybase + i - h;
+            if (i >= 2 * h && o < H) {
+                float cq = 0.0f;                                     // rows o-R .. o+R
+#pragma unroll
+                for (int j = 0; j <= 2 * R; ++j)
+                    cq = fmaf(w[j], dwin[((ph - R - 2 + j) % kP + kP) % kP], cq);
+                const float pro = prw[((ph - 2) % kP + kP) % kP];
+                const float anv = cur.oa;
+                const bool mk = cur.omk != 0;
+                const float rv = mk ? 0.0f : anv;
+                float acv = fmaf(s.alpha, fmaf(-s.tau, pro + cq, rv), cur.oc);
+                const float back = (1.0f - s.alpha) * rv;
+                const unsigned ro = (unsigned)(o - b0) * W4;
+                if (s.first) acv += back;
+                else __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(back), rs_ap, vo4, ro, 0);
+                if (mk) acv += anv;                                  // known pixel: running sum
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acv), rs_ac, vo4, ro, 0);
+            }
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) dsum += __shfl_down(dsum, off, 64);
+    // every lane stores lane 0's running total (no lane-dependent branch)
+    const double tot = lane0_double(dsum);
+    const double prev = partial[0];
+    partial[0] = prev + (double)lam_scale * tot;
+}
+
+template <int R, int ROWS>
+__global__ __launch_bounds__(256) void adjoint_strip_kernel(const float *u_all, const float *an_all,
+                                                            float *ac_all, float *ap_all,
+                                                            const uint8_t *__restrict__ mask_all,
+                                                            int H, int W, int nstrip, int per_img,
+                                                            int nitems, StepArgs a, float il3,
+                                                            float lam_scale, int first,
+                                                            double *lam_partials)
+{
+    using G = AdjStripGeo<R, ROWS>;
+    // one pad float at each end: at radius 0 the Hessian of lane 0 (63) reads
+    // one element left (right) of its ring row
+    __shared__ float lds[4 * G::LDS + 2];
+    const int wave = threadIdx.x >> 6;
+    const int item = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + wave);
+    if (item >= nitems) return;  // whole wave; the kernel has no workgroup barrier
+    const int b = item / per_img;
+    const int r = item - b * per_img;
+    const int seg = r / nstrip, strip = r - seg * nstrip;
+    const size_t off = (size_t)b * H * W;
+    AdjStripArgs s;
+    s.u = u_all + off;
+    s.an = an_all + off;
+    s.ac = ac_all + off;
+    s.ap = ap_all + off;
+    s.mask = mask_all + off;
+    s.H = H;
+    s.W = W;
+    s.X0 = strip * G::SW;
+    s.Y0 = seg * G::OH;
+    s.tau = a.tau;
+    s.alpha = a.alpha;
+    s.il2 = a.inv_lam2;
+    s.il3 = il3;
+    s.first = first;
+    adjoint_strip_step<R, ROWS>(lds + 1 + wave * G::LDS, s, a.w, lam_partials + 2 * (size_t)item,
+                                lam_scale);
 }
 
 // ---- small helper kernels ----
@@ -305,7 +612,7 @@ __global__ __launch_bounds__(256) void fill_double_kernel(double *p, size_t n)
         p[i] = 0.0;
 }
 
-// acc[b] += fixed-order sum of image b's tile partials (first double of each)
+// acc[b] = fixed-order sum of image b's work-item partials (first double of each)
 __global__ __launch_bounds__(256) void lambda_reduce_kernel(const double *partials,
                                                             int tiles_per_img, double *acc)
 {
@@ -320,7 +627,7 @@ __global__ __launch_bounds__(256) void lambda_reduce_kernel(const double *partia
         if (threadIdx.x < s) sd[threadIdx.x] += sd[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) acc[b] += sd[0];
+    if (threadIdx.x == 0) acc[b] = sd[0];
 }
 
 __global__ void lambda_store_kernel(const double *acc, float *out, int B)
@@ -329,19 +636,18 @@ __global__ void lambda_store_kernel(const double *acc, float *out, int B)
     if (b < B) out[b] = (float)acc[b];
 }
 
-// fbar += m * ubar^{0,0}; dL/du_init = mbar * ubar^{0,0}
+// On known pixels abar0 holds the sum of ubar over every state (ubar^{0,0}
+// included): that is dL/df.  Elsewhere abar0 = ubar^{0,0} = dL/du_init.
 __global__ __launch_bounds__(256) void adjoint_final_kernel(const float *abar0,
                                                             const uint8_t *__restrict__ mask,
                                                             float *gk, float *gi, size_t n)
 {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x) {
-        if (mask[i]) {
-            gk[i] += abar0[i];
-            gi[i] = 0.0f;
-        } else {
-            gi[i] = abar0[i];
-        }
+        const float v = abar0[i];
+        const bool m = mask[i] != 0;
+        gk[i] = m ? v : 0.0f;
+        gi[i] = m ? 0.0f : v;
     }
 }
 
@@ -351,33 +657,28 @@ static unsigned grid_for(size_t n)
     return (unsigned)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
 }
 
-int adjoint_tiles_per_image(int H, int W)
+static int adjoint_tiles_per_image(int H, int W)
 {
     return ((W + kAdjTW - 1) / kAdjTW) * ((H + kAdjTH - 1) / kAdjTH);
 }
 
-template <int R>
-static hipError_t launch_a_t(const float *u, const float *an, const uint8_t *mask, int B, int H,
-                             int W, const StepArgs &a, float lam, float lam_scale, float *qx,
-                             float *qy, float *pr, double *lp, hipStream_t s)
+template <int R, int ROWS>
+static int adj_strip_items_t(int H, int W)
 {
-    const int nbx = (W + kAdjTW - 1) / kAdjTW;
-    const int tpi = adjoint_tiles_per_image(H, W);
-    hipLaunchKernelGGL((adjoint_a_kernel<R>), dim3((unsigned)(tpi * B)), dim3(256), 0, s, u, an,
-                       mask, H, W, nbx, tpi, a, lam, lam_scale, qx, qy, pr, lp);
-    return hipGetLastError();
+    using G = AdjStripGeo<R, ROWS>;
+    return ((W + G::SW - 1) / G::SW) * ((H + G::OH - 1) / G::OH);
 }
 
 template <int R>
-static hipError_t launch_b_t(const float *qx, const float *qy, const float *pr, float *an,
-                             float *ac, const uint8_t *mask, float *gk, int B, int H, int W,
-                             const StepArgs &a, int first, hipStream_t s)
+static int adj_items_r(int shape, int H, int W)
 {
-    const int nbx = (W + kAdjTW - 1) / kAdjTW;
-    const int tpi = adjoint_tiles_per_image(H, W);
-    hipLaunchKernelGGL((adjoint_b_kernel<R>), dim3((unsigned)(tpi * B)), dim3(256), 0, s, qx, qy,
-                       pr, an, ac, mask, gk, H, W, nbx, tpi, a, first);
-    return hipGetLastError();
+    switch (shape) {
+    case kShapeStrip: return adj_strip_items_t<R, 64>(H, W);
+    case kShapeStripTall: return adj_strip_items_t<R, 136>(H, W);
+    case kShapeStripShort: return adj_strip_items_t<R, 28>(H, W);
+    case kShapeStripTiny: return adj_strip_items_t<R, 8>(H, W);
+    default: return adjoint_tiles_per_image(H, W);
+    }
 }
 
 #define EED4_RSWITCH(CALL)                                                          \
@@ -385,54 +686,122 @@ static hipError_t launch_b_t(const float *qx, const float *qy, const float *pr, 
     case 0: return CALL(0); case 1: return CALL(1); case 2: return CALL(2);         \
     case 3: return CALL(3); case 4: return CALL(4); case 5: return CALL(5);         \
     case 6: return CALL(6); case 7: return CALL(7); case 8: return CALL(8);         \
-    default: return hipErrorInvalidValue;                                           \
+    default: break;                                                                 \
     }
 
-hipError_t launch_adjoint_a(int R, const float *u, const float *an, const uint8_t *mask, int B,
-                            int H, int W, const StepArgs &a, float lam, float lam_scale,
-                            float *qx, float *qy, float *pr, double *lp, hipStream_t s)
+// Work items per image of a reverse step: tiles (shapes 0..2, one adjoint
+// tile shape) or strip segments of the given height.
+static int adjoint_items(int R, int shape, int H, int W)
 {
-#define EED4_CALL_A(r) launch_a_t<r>(u, an, mask, B, H, W, a, lam, lam_scale, qx, qy, pr, lp, s)
-    EED4_RSWITCH(EED4_CALL_A)
-#undef EED4_CALL_A
+#define EED4_CALL_N(r) adj_items_r<r>(shape, H, W)
+    EED4_RSWITCH(EED4_CALL_N)
+#undef EED4_CALL_N
+    return 0;
 }
 
-hipError_t launch_adjoint_b(int R, const float *qx, const float *qy, const float *pr, float *an,
-                            float *ac, const uint8_t *mask, float *gk, int B, int H, int W,
-                            const StepArgs &a, int first, hipStream_t s)
+static int max_adjoint_items(int R, int H, int W)
 {
-#define EED4_CALL_B(r) launch_b_t<r>(qx, qy, pr, an, ac, mask, gk, B, H, W, a, first, s)
-    EED4_RSWITCH(EED4_CALL_B)
-#undef EED4_CALL_B
+    int m = 0;
+    for (int sh = 0; sh < kNumShapes; ++sh) m = std::max(m, adjoint_items(R, sh, H, W));
+    return m;
 }
 
-hipError_t launch_fill(float *p, size_t n, float v, hipStream_t s)
+// Buffers of one reverse step.
+struct RevStep {
+    const float *u, *an;     // u^k, ubar^{k+1}
+    float *ac, *ap;          // ubar^k (in place), ubar^{k-1} contribution
+    float *qx, *qy, *pr;     // tile path only
+    const uint8_t *mask;
+    double *lp;              // lambda partials, one slot per work item
+    int B, H, W, R, shape, first;
+};
+
+template <int R>
+static hipError_t launch_rev_tile(const RevStep &t, const StepArgs &a, float il3, float ls,
+                                  hipStream_t s)
+{
+    const int nbx = (t.W + kAdjTW - 1) / kAdjTW;
+    const int tpi = adjoint_tiles_per_image(t.H, t.W);
+    hipLaunchKernelGGL((adjoint_a_kernel<R>), dim3((unsigned)(tpi * t.B)), dim3(256), 0, s, t.u,
+                       t.an, t.mask, t.H, t.W, nbx, tpi, a, il3, ls, t.qx, t.qy, t.pr, t.lp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((adjoint_b_kernel<R>), dim3((unsigned)(tpi * t.B)), dim3(256), 0, s, t.qx,
+                       t.qy, t.pr, t.an, t.ac, t.ap, t.mask, t.H, t.W, nbx, tpi, a, t.first);
+    return hipGetLastError();
+}
+
+template <int R, int ROWS>
+static hipError_t launch_rev_strip(const RevStep &t, const StepArgs &a, float il3, float ls,
+                                   hipStream_t s)
+{
+    using G = AdjStripGeo<R, ROWS>;
+    const int nstrip = (t.W + G::SW - 1) / G::SW;
+    const int per_img = adj_strip_items_t<R, ROWS>(t.H, t.W);
+    const long long nitems = (long long)per_img * t.B;
+    if (nitems > (1LL << 31) - 4) return hipErrorInvalidValue;
+    const unsigned nblk = (unsigned)((nitems + 3) / 4);
+    hipLaunchKernelGGL((adjoint_strip_kernel<R, ROWS>), dim3(nblk), dim3(256), 0, s, t.u, t.an,
+                       t.ac, t.ap, t.mask, t.H, t.W, nstrip, per_img, (int)nitems, a, il3, ls,
+                       t.first, t.lp);
+    return hipGetLastError();
+}
+
+template <int R>
+static hipError_t launch_rev_r(const RevStep &t, const StepArgs &a, float il3, float ls,
+                               hipStream_t s)
+{
+    switch (t.shape) {
+    case kShapeStrip: return launch_rev_strip<R, 64>(t, a, il3, ls, s);
+    case kShapeStripTall: return launch_rev_strip<R, 136>(t, a, il3, ls, s);
+    case kShapeStripShort: return launch_rev_strip<R, 28>(t, a, il3, ls, s);
+    case kShapeStripTiny: return launch_rev_strip<R, 8>(t, a, il3, ls, s);
+    default: return launch_rev_tile<R>(t, a, il3, ls, s);
+    }
+}
+
+// One reverse step k (alpha_k, lambda scale -alpha_k tau).
+static hipError_t launch_reverse_step(const RevStep &t, const eed4_params *p, int k,
+                                      hipStream_t s)
+{
+    const StepArgs a = make_args(p->sigma, t.R, p->tau, p->lambda, k);
+    const float il3 = (float)(1.0 / ((double)p->lambda * p->lambda * p->lambda));
+    const float ls = -a.alpha * a.tau;
+    const int R = t.R;
+#define EED4_CALL_REV(r) launch_rev_r<r>(t, a, il3, ls, s)
+    EED4_RSWITCH(EED4_CALL_REV)
+#undef EED4_CALL_REV
+    return hipErrorInvalidValue;
+}
+#undef EED4_RSWITCH
+
+static hipError_t launch_fill(float *p, size_t n, float v, hipStream_t s)
 {
     hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 
-hipError_t launch_fill_double(double *p, size_t n, hipStream_t s)
+static hipError_t launch_fill_double(double *p, size_t n, hipStream_t s)
 {
     hipLaunchKernelGGL(fill_double_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 
-hipError_t launch_lambda_reduce(const double *lp, int tiles_per_img, int B, double *acc,
-                                hipStream_t s)
+static hipError_t launch_lambda_reduce(const double *lp, int items_per_img, int B, double *acc,
+                                       hipStream_t s)
 {
-    hipLaunchKernelGGL(lambda_reduce_kernel, dim3(B), dim3(256), 0, s, lp, tiles_per_img, acc);
+    hipLaunchKernelGGL(lambda_reduce_kernel, dim3(B), dim3(256), 0, s, lp, items_per_img, acc);
     return hipGetLastError();
 }
 
-hipError_t launch_lambda_store(const double *acc, float *out, int B, hipStream_t s)
+static hipError_t launch_lambda_store(const double *acc, float *out, int B, hipStream_t s)
 {
     hipLaunchKernelGGL(lambda_store_kernel, dim3((B + 255) / 256), dim3(256), 0, s, acc, out, B);
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint_final(const float *abar0, const uint8_t *mask, float *gk, float *gi,
-                                size_t n, hipStream_t s)
+static hipError_t launch_adjoint_final(const float *abar0, const uint8_t *mask, float *gk,
+                                       float *gi, size_t n, hipStream_t s)
 {
     hipLaunchKernelGGL(adjoint_final_kernel, dim3(grid_for(n)), dim3(256), 0, s, abar0, mask, gk,
                        gi, n);
@@ -441,22 +810,23 @@ hipError_t launch_adjoint_final(const float *abar0, const uint8_t *mask, float *
 
 // ---- workspace layout of eed4_backward ----
 struct BackwardLayout {
-    size_t U, an, ac, qx, qy, pr, lp, acc, total;
+    size_t U, an, ac, ap, qx, qy, pr, lp, acc, total;
 };
 
-static BackwardLayout backward_layout(int B, int H, int W, int n)
+static BackwardLayout backward_layout(int B, int H, int W, int n, int R)
 {
     BackwardLayout L{};
     const size_t N = (size_t)B * H * W;
-    const size_t tiles = (size_t)adjoint_tiles_per_image(H, W) * B;
+    const size_t items = (size_t)max_adjoint_items(R, H, W) * B;
     size_t o = 0;
     L.U = o; o = align_up(o + sizeof(float) * N * (size_t)(n > 1 ? n - 1 : 1));
     L.an = o; o = align_up(o + sizeof(float) * N);
     L.ac = o; o = align_up(o + sizeof(float) * N);
+    L.ap = o; o = align_up(o + sizeof(float) * N);
     L.qx = o; o = align_up(o + sizeof(float) * N);
     L.qy = o; o = align_up(o + sizeof(float) * N);
     L.pr = o; o = align_up(o + sizeof(float) * N);
-    L.lp = o; o = align_up(o + sizeof(double) * 2 * tiles);
+    L.lp = o; o = align_up(o + sizeof(double) * 2 * items);
     L.acc = o; o = align_up(o + sizeof(double) * (size_t)B);
     L.total = o;
     return L;
@@ -464,7 +834,61 @@ static BackwardLayout backward_layout(int B, int H, int W, int n)
 
 size_t backward_workspace(int B, int H, int W, const eed4_params *p)
 {
-    return backward_layout(B, H, W, p->cycle_len).total;
+    const int R = eed4_radius(p->sigma);
+    return R < 0 ? 0 : backward_layout(B, H, W, p->cycle_len, R).total;
+}
+
+static std::string adjoint_tune_key(int R, int B, int H, int W)
+{
+    char buf[96];
+    std::snprintf(buf, sizeof(buf), "adjoint_R%d_B%d_H%d_W%d", R, B, H, W);
+    return buf;
+}
+
+// Reverse-step implementation: a forced shape (tile shapes select the tile
+// passes, strip shapes the strip kernel of that height), else the tuned
+// choice for this problem size, else the timing of one reverse step of each
+// on the caller's data (t holds real buffers; what it writes is scratch).
+static int adjoint_shape(const eed4_params *p, RevStep t, hipStream_t s, int *shape)
+{
+    const int forced = (p->flags >> 8) & 0xff;
+    if (forced >= 1 && forced <= kNumShapes) { *shape = forced - 1; return EED4_OK; }
+    if (p->flags & EED4_TILE_KERNEL) { *shape = 0; return EED4_OK; }
+    const std::string key = adjoint_tune_key(t.R, t.B, t.H, t.W);
+    if (tune_lookup(key, shape)) return EED4_OK;
+    const int cands[] = {0, kShapeStrip, kShapeStripTall, kShapeStripShort, kShapeStripTiny};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    const size_t N = (size_t)t.B * t.H * t.W;
+    if (e == hipSuccess) e = launch_fill(t.ac, N, 0.0f, s);
+    int best = 0;
+    float bt = 1e30f;
+    for (int c : cands) {
+        if (e != hipSuccess) break;
+        t.shape = c;
+        t.first = 0;
+        float tmin = 1e30f;
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+            e = hipEventRecord(e0, s);
+            if (e == hipSuccess) e = launch_reverse_step(t, p, p->cycle_len - 1, s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && rep > 0) tmin = std::fmin(tmin, ms);   // first run warms up
+        }
+        if (e == hipSuccess && tmin < bt) {
+            bt = tmin;
+            best = c;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "adjoint autotune");
+    tune_remember(key, best);
+    *shape = best;
+    return EED4_OK;
 }
 
 }  // namespace eed4
@@ -481,17 +905,27 @@ extern "C" int eed4_backward(const float *ckpt, const uint8_t *mask, const float
     if (!ckpt || !mask || !known || !grad_u || !grad_known || !grad_init || !grad_lambda || M < 1)
         return EED4_EINVAL;
     const int n = p->cycle_len, R = eed4_radius(p->sigma);
-    BackwardLayout L = backward_layout(B, H, W, n);
+    BackwardLayout L = backward_layout(B, H, W, n, R);
     if ((rc = check_ws(ws, ws_bytes, L.total)) != EED4_OK) return rc;
     char *base = (char *)ws;
     hipStream_t s = (hipStream_t)stream;
     const size_t N = (size_t)B * H * W;
     float *Ubuf = (float *)(base + L.U);
-    float *an = (float *)(base + L.an), *ac = (float *)(base + L.ac);
-    float *qx = (float *)(base + L.qx), *qy = (float *)(base + L.qy), *pr = (float *)(base + L.pr);
-    double *lp = (double *)(base + L.lp), *acc = (double *)(base + L.acc);
-    const int tpi = adjoint_tiles_per_image(H, W);
-    const int shape = step_shape(p, B, H, W);
+    double *acc = (double *)(base + L.acc);
+    RevStep t{};
+    t.an = (float *)(base + L.an);
+    t.ac = (float *)(base + L.ac);
+    t.ap = (float *)(base + L.ap);
+    t.qx = (float *)(base + L.qx);
+    t.qy = (float *)(base + L.qy);
+    t.pr = (float *)(base + L.pr);
+    t.mask = mask;
+    t.lp = (double *)(base + L.lp);
+    t.B = B;
+    t.H = H;
+    t.W = W;
+    t.R = R;
+    const int fshape = step_shape(p, B, H, W);      // forward recompute
     hipError_t e;
 #define EED4_TRY(x, what)                                    \
     do {                                                     \
@@ -499,38 +933,46 @@ extern "C" int eed4_backward(const float *ckpt, const uint8_t *mask, const float
         if (e != hipSuccess) return hip_fail(e, what);       \
     } while (0)
 
-    EED4_TRY(launch_fill(grad_known, N, 0.0f, s), "fill");
-    EED4_TRY(launch_fill_double(acc, (size_t)B, s), "fill");
-    EED4_TRY(hipMemcpyAsync(an, grad_u, sizeof(float) * N, hipMemcpyDeviceToDevice, s), "seed copy");
+    {   // choose the reverse-step kernel (the timing runs write only scratch)
+        RevStep probe = t;
+        probe.u = ckpt + (size_t)(M - 1) * N;
+        probe.an = grad_u;
+        if ((rc = adjoint_shape(p, probe, s, &t.shape)) != EED4_OK) return rc;
+    }
+    const int items = adjoint_items(R, t.shape, H, W);
+    EED4_TRY(launch_fill_double(t.lp, 2 * (size_t)items * B, s), "fill");
+    EED4_TRY(hipMemcpyAsync((void *)t.an, grad_u, sizeof(float) * N, hipMemcpyDeviceToDevice, s),
+             "seed copy");
     std::vector<const float *> U(n);
+    float *an = (float *)t.an, *ac = t.ac, *ap = t.ap;
     for (int m = M - 1; m >= 0; --m) {
         // recompute u^{m,1..n-1} from the checkpoint
         U[0] = ckpt + (size_t)m * N;
         for (int k = 0; k + 1 < n; ++k) {
             float *out = Ubuf + (size_t)k * N;
             StepArgs a = make_args(p->sigma, R, p->tau, p->lambda, k);
-            EED4_TRY(launch_step(R, shape, U[k], U[k > 0 ? k - 1 : 0], out, nullptr, mask, B, H,
+            EED4_TRY(launch_step(R, fshape, U[k], U[k > 0 ? k - 1 : 0], out, nullptr, mask, B, H,
                                  W, a, nullptr, s),
                      "recompute step");
             U[k + 1] = out;
         }
         EED4_TRY(launch_fill(ac, N, 0.0f, s), "fill");
         for (int k = n - 1; k >= 0; --k) {
-            StepArgs a = make_args(p->sigma, R, p->tau, p->lambda, k);
-            const float lam_scale = -a.alpha * a.tau;
-            EED4_TRY(launch_adjoint_a(R, U[k], an, mask, B, H, W, a, p->lambda, lam_scale, qx, qy,
-                                      pr, lp, s),
-                     "adjoint pass A");
-            EED4_TRY(launch_lambda_reduce(lp, tpi, B, acc, s), "lambda reduce");
-            EED4_TRY(launch_adjoint_b(R, qx, qy, pr, an, ac, mask, grad_known, B, H, W, a,
-                                      k == 0 ? 1 : 0, s),
-                     "adjoint pass B");
-            float *t = an;
+            t.u = U[k];
+            t.an = an;
+            t.ac = ac;
+            t.ap = ap;
+            t.first = k == 0 ? 1 : 0;
+            EED4_TRY(launch_reverse_step(t, p, k, s), "reverse step");
+            // ubar^k is complete in ac; ap holds the start of ubar^{k-1}
+            float *tmp = an;
             an = ac;
-            ac = t;
+            ac = ap;
+            ap = tmp;
         }
     }
     EED4_TRY(launch_adjoint_final(an, mask, grad_known, grad_init, N, s), "final");
+    EED4_TRY(launch_lambda_reduce(t.lp, items, B, acc, s), "lambda reduce");
     EED4_TRY(launch_lambda_store(acc, grad_lambda, B, s), "lambda store");
 #undef EED4_TRY
     return EED4_OK;

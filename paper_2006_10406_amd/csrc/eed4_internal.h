@@ -43,24 +43,6 @@ constexpr int strip_target_rows(int shape)
                                      : 64;
 }
 
-// Device-side descriptor of one image of an uneven batch.
-struct ImageDesc {
-    float *S;              // caller's u: cycle-start state and result
-    float *X, *Y;          // two workspace rotation buffers
-    const uint8_t *mask;
-    const float *known;
-    int H, W;
-    int nbx;               // tiles per row
-    int tile0;             // first tile of this image in the full tile list
-    float inv_lam2;
-    int pad;
-};
-
-// One queue entry of the batched persistent kernel.
-struct TileRef {
-    int img, ty, tx, slot;  // slot: index of the residual partial of this tile
-};
-
 // ---- launchers (eed4_forward.hip) ----
 hipError_t launch_hold(float *u, const uint8_t *mask, const float *known, size_t n,
                        hipStream_t s);

@@ -98,6 +98,27 @@ __device__ __forceinline__ float buf_f32(__amdgpu_buffer_rsrc_t r, unsigned voff
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
 
+// Image row of consecutive stream rows under the half-sample mirror: the row
+// moves in direction dir; at an edge it repeats once and the direction flips.
+struct RowTrack {
+    int y, dir;
+    __device__ __forceinline__ void init(int y0, int H)
+    {
+        y = mirror_reflect(y0, H);
+        const int k = y0 >= 0 ? y0 / H : -1 - (-1 - y0) / H;   // mirror copy index
+        dir = (k & 1) ? -1 : 1;
+    }
+    __device__ __forceinline__ void next(int H)
+    {
+        int nx = y + dir;
+        if ((unsigned)nx >= (unsigned)H) {
+            dir = -dir;
+            nx = y;
+        }
+        y = nx;
+    }
+};
+
 // Global loads of one stream row: u^k of the row itself, and u^{k-1}, the
 // mask and the residual reference of the output row it serves.
 struct StripRow {
@@ -155,21 +176,15 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
     float uc_p = 0.0f;                                   // u^k(g-1, c)
     double d2 = 0.0, n2 = 0.0;
 
-    // Row trackers of the next row to prefetch: its mirrored image row ym
-    // (moving in direction ydir; at an edge the row repeats and the direction
-    // flips, which is the half-sample mirror) and the output row it serves.
-    int ym = mirror_reflect(ybase, H);
-    int ydir;
-    {
-        const int k = ybase >= 0 ? ybase / H : -1 - (-1 - ybase) / H;   // mirror copy index
-        ydir = (k & 1) ? -1 : 1;
-    }
+    // the next row to prefetch: its mirrored image row and the output row it serves
+    RowTrack ty;
+    ty.init(ybase, H);
     int on = ybase - R - 2;
 
     // Loads run two stream rows ahead, always in the same order, so waiting
     // for one row never waits for a later row's loads.
     auto prefetch = [&](StripRow &r) {
-        const unsigned su = (unsigned)((ym > b0 ? ym : b0) - b0) * W4;
+        const unsigned su = (unsigned)((ty.y > b0 ? ty.y : b0) - b0) * W4;
         r.a = buf_f32(rs_u, ca, su);
         if constexpr (R > 0) r.b = buf_f32(rs_u, cb, su);
         int oc = on < b0 ? b0 : on;                      // clamped; unused rows are not stored
@@ -178,12 +193,7 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
         r.pv = buf_f32(rs_p, vo4, ro * W4);
         r.mk = __builtin_amdgcn_raw_buffer_load_b8(rs_m, vo1, ro * (unsigned)W, 0);
         if constexpr (RES) r.rf = buf_f32(rs_r, vo4, ro * W4);
-        int nx = ym + ydir;
-        if ((unsigned)nx >= (unsigned)H) {
-            ydir = -ydir;
-            nx = ym;
-        }
-        ym = nx;
+        ty.next(H);
         ++on;
     };
     StripRow r0, r1;

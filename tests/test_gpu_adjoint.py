@@ -65,6 +65,21 @@ def test_adjoint_matches_oracle(H, W, sigma, lam, n, M):
     compare(b, ck, gk, gi, gl, lam, sigma, 0.05, n, gu, f"{H}x{W} s{sigma} n{n}")
 
 
+@pytest.mark.parametrize("shape", range(len(eed4.SHAPE_NAMES)))
+@pytest.mark.parametrize("H,W,sigma,n", [(75, 140, 1.0, 4), (131, 62, 2.0, 3), (7, 200, 0.5, 2)])
+def test_each_reverse_step_kernel_matches_oracle(shape, H, W, sigma, n):
+    # tile shapes select the two-pass tile adjoint, strip shapes the fused
+    # strip adjoint of that segment height (and the same forward shape)
+    announce(f"reverse step {eed4.SHAPE_NAMES[shape]} {H}x{W} sigma={sigma} n={n}")
+    b = {k: np.stack([make_problem(H, W, 5, True, 0.01, 0.06, 700 + i + W)[k] for i in range(2)])
+         for k in ("image", "mask", "known", "u_init")}
+    gu = np.random.default_rng(H + W).normal(size=b["u_init"].shape) * 1e-2
+    _, ck, gk, gi, gl = gpu_forward_backward(b, 0.04, sigma, 0.05, n, 2, gu,
+                                             flags=eed4.EED4_FORCE_SHAPE(shape))
+    compare(b, ck, gk, gi, gl, 0.04, sigma, 0.05, n, gu,
+            f"{eed4.SHAPE_NAMES[shape]} {H}x{W} s{sigma}")
+
+
 def test_adjoint_tile_kernel_recompute():
     announce("adjoint with the tile step kernel for the recompute")
     b = {k: v[None] for k, v in make_problem(48, 60, 4, True, 0.01, 0.06, 31).items()
