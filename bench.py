@@ -198,6 +198,37 @@ def batched_vs_single(eed4, torch, cycles):
             "autotuned_shape": eed4.SHAPE_NAMES[shape], "max_rmse_between": diff}
 
 
+def adjoint_probe(eed4, torch):
+    """Backward passes for kernel traces: the 16 x 256x256 workload (30 cycles of 10) and one
+    cycle of 15 on the 4096x4096 workload, each after its forward with checkpoints."""
+    from synth import WORKLOADS, make_batch, make_problem
+
+    def run(u0, mask, known, wl, M, label):
+        B, H, W = u0.shape
+        p = eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, M)
+        ck = torch.empty((M, B, H, W), dtype=torch.float32, device="cuda")
+        u = u0.clone()
+        eed4.eed4_inpaint(u, mask, known, p, ckpt=ck)
+        gu = torch.randn((B, H, W), device="cuda") * 1e-3
+        gk, gi = torch.empty_like(gu), torch.empty_like(gu)
+        gl = torch.empty(B, device="cuda")
+        for rep in range(2):          # the first call also picks the reverse-step kernel
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            eed4.eed4_backward(ck, mask, known, p, M, gu, gk, gi, gl)
+            torch.cuda.synchronize()
+            log(f"{label}: backward {(time.perf_counter() - t) * 1e3:.2f} ms")
+
+    wl = WORKLOADS["adjoint16"]
+    b = make_batch(wl)
+    dev = lambda a: torch.from_numpy(a).cuda()
+    run(dev(b["u_init"]), dev(b["mask"]), dev(b["known"]), wl, wl.M, "adjoint16")
+    wl = WORKLOADS["large4096"]
+    pr = make_problem(wl.H, wl.W, wl.n_ellipses, wl.ramp, wl.noise_std, wl.density, wl.seed_base)
+    one = lambda a: torch.from_numpy(a).cuda()[None].contiguous()
+    run(one(pr["u_init"]), one(pr["mask"]), one(pr["known"]), wl, 1, "large4096, one cycle")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -209,6 +240,9 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-cycles", type=int, default=40)
+    ap.add_argument("--adjoint-probe", action="store_true",
+                    help="backward passes only (16 x 256x256 and one 4096x4096 cycle), for "
+                         "kernel traces of the reverse-step kernels")
     ap.add_argument("--probe", action="store_true",
                     help="counter probe: 3 cycles of fused step launches on the workload, then "
                          "a plain 64 MiB device copy (calibrates FETCH_SIZE / WRITE_SIZE)")
@@ -223,6 +257,10 @@ def main():
 
     import paper_2006_10406_amd as eed4
     from synth import WORKLOADS, make_problem
+
+    if args.adjoint_probe:
+        adjoint_probe(eed4, torch)
+        return
 
     wl = WORKLOADS["large4096"]
     log(f"generating {wl.name} {wl.H}x{wl.W}")
@@ -279,16 +317,22 @@ def main():
             return b, a, c
         return (b, c, c) if k % 2 else (c, b, b)
 
-    launches = 0
-    e2.record(stream)
-    for _ in range(args.kernel_reps):
-        for k in range(n):
-            cur, prev, out = roles(k)
-            eed4.eed4_fsi_step(cur, prev, out, mask, ps, k, stream=stream)
-            launches += 1
-    e3.record(stream)
-    torch.cuda.synchronize()
-    kms = e2.elapsed_time(e3) / launches
+    # three windows of kernel_reps cycles each; the median window is reported
+    # (the first launches after a pause run at a lower clock)
+    windows = []
+    for _ in range(3):
+        launches = 0
+        e2.record(stream)
+        for _ in range(args.kernel_reps):
+            for k in range(n):
+                cur, prev, out = roles(k)
+                eed4.eed4_fsi_step(cur, prev, out, mask, ps, k, stream=stream)
+                launches += 1
+        e3.record(stream)
+        torch.cuda.synchronize()
+        windows.append(e2.elapsed_time(e3) / launches)
+    kms = sorted(windows)[1]
+    log("fused step windows: " + ", ".join(f"{w * 1e3:.1f}" for w in windows) + " us/launch")
     per_launch_bytes = BYTES_PER_UPDATE * H * W
     achieved = per_launch_bytes / (kms * 1e-3) / 1e9
     R = eed4.eed4_radius(wl.sigma)

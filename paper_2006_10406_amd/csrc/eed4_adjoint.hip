@@ -342,11 +342,12 @@ struct AdjStripGeo {
     static constexpr int hc = R + 2;                          // first output lane
     static constexpr int SW = 64 - 2 * hc;                    // output columns per wave
     static constexpr int NU = 64 + 2 * R;                     // staged u columns per row
+    static constexpr int CS = D | 1;                          // ring column stride (odd)
     static constexpr int ND = 64 + 2 * R;                     // d row, R pad on each side
     static constexpr int M = (ROWS + 2 * h - 2 * R + U - 1) / U;
     static constexpr int NROW = 2 * R + M * U;                // rows streamed per wave
     static constexpr int OH = NROW - 2 * h;                   // output rows per wave
-    static constexpr int LDS = D * NU + ND;                   // floats of LDS per wave
+    static constexpr int LDS = (NU + 2) * CS + ND;            // floats of LDS per wave
 };
 
 struct AdjStripArgs {
@@ -399,9 +400,12 @@ __device__ __forceinline__ void adjoint_strip_step(float *ring, const AdjStripAr
     const unsigned vo1 = out_lane ? (unsigned)cl : kOffNone;
     const int yend = s.Y0 + G::OH < H ? s.Y0 + G::OH : H;     // rows owned: [Y0, yend)
 
-    float *rl = ring + lane;                                  // u ring row r at r * NU
-    float *rb = ring + 64 + lb;
-    float *dw = ring + D * NU + lane;                         // d row: lane l at l + R
+    // u ring column-major as in the forward strip: staged column c of ring
+    // row r at (c + 1) * CS + r; then the d row (lane l at l + R)
+    constexpr int CS = G::CS;
+    float *col = ring + (lane + 1) * CS;
+    float *bcol = ring + (64 + lb + 1) * CS;
+    float *dw = ring + (NU + 2) * CS + lane;
 
     float win[P], dwin[P], prw[P];    // x-pass u, x-pass d, P(u) r; row j in slot j % P
 #pragma unroll
@@ -445,13 +449,12 @@ __device__ __forceinline__ void adjoint_strip_step(float *ring, const AdjStripAr
         const AdjStripRow cur = r0;
         r0 = r1;
         prefetch(r1);
-        rl[(i % D) * NU] = cur.a;
-        rb[(i % D) * NU] = cur.b;
+        col[i % D] = cur.a;
+        bcol[i % D] = cur.b;
         wave_lds_sync();
-        const float *slot = rl + (i % D) * NU;
-        float acc = w[0] * slot[0];
+        float acc = w[0] * col[i % D];
 #pragma unroll
-        for (int j = 1; j <= 2 * R; ++j) acc = fmaf(w[j], slot[j], acc);
+        for (int j = 1; j <= 2 * R; ++j) acc = fmaf(w[j], col[j * CS + i % D], acc);
         win[i % P] = acc;
         r_m1 = r_0;
         r_0 = cur.rmk ? 0.0f : cur.rn;
@@ -468,13 +471,12 @@ __device__ __forceinline__ void adjoint_strip_step(float *ring, const AdjStripAr
 
             // ---- S1: stage u^k row i, x pass ----
             const int sr = (2 * R + ph) % D;                 // constants once unrolled
-            rl[sr * NU] = cur.a;
-            if constexpr (R > 0) rb[sr * NU] = cur.b;
+            col[sr] = cur.a;
+            if constexpr (R > 0) bcol[sr] = cur.b;
             wave_lds_sync();
-            const float *slot = rl + sr * NU;
-            float acc = w[0] * slot[0];
+            float acc = w[0] * col[sr];
 #pragma unroll
-            for (int j = 1; j <= 2 * R; ++j) acc = fmaf(w[j], slot[j], acc);
+            for (int j = 1; j <= 2 * R; ++j) acc = fmaf(w[j], col[j * CS + sr], acc);
             win[(2 * R + ph) % P] = acc;
 
             // ---- S2: y pass at stream row i - R ----
@@ -487,13 +489,13 @@ __device__ __forceinline__ void adjoint_strip_step(float *ring, const AdjStripAr
             const float gys = v - v_m2;                                      // 2 gy
             v_m2 = v_m1;
             v_m1 = v;
-            const float *um = rl + ((R - 2 + ph + D) % D) * NU + R;    // row g - 1
-            const float *u0 = rl + ((R - 1 + ph + D) % D) * NU + R;    // row g
-            const float *up = rl + ((R + ph) % D) * NU + R;            // row g + 1
+            const float *um = col + R * CS + (R - 2 + ph + D) % D;     // rows g-1, g, g+1
+            const float *u0 = col + R * CS + (R - 1 + ph + D) % D;
+            const float *up = col + R * CS + (R + ph) % D;
             const float uc = u0[0];
-            const float hxx = fmaf(-2.0f, uc, u0[-1] + u0[1]);
+            const float hxx = fmaf(-2.0f, uc, u0[-CS] + u0[CS]);
             const float hyy = fmaf(-2.0f, uc, um[0] + up[0]);
-            const float hxy = 0.25f * ((up[1] + um[-1]) - (up[-1] + um[1]));
+            const float hxy = 0.25f * ((up[CS] + um[-CS]) - (up[-CS] + um[CS]));
             const float r_p1 = cur.rmk ? 0.0f : cur.rn;                // r at row g + 1
             const float axx = fmaf(-2.0f, r_0, from_prev_lane(r_0) + from_next_lane(r_0));
             const float ayy = fmaf(-2.0f, r_0, r_m1 + r_p1);
@@ -568,9 +570,7 @@ __global__ __launch_bounds__(256) void adjoint_strip_kernel(const float *u_all, 
                                                             double *lam_partials)
 {
     using G = AdjStripGeo<R, ROWS>;
-    // one pad float at each end: at radius 0 the Hessian of lane 0 (63) reads
-    // one element left (right) of its ring row
-    __shared__ float lds[4 * G::LDS + 2];
+    __shared__ float lds[4 * G::LDS];
     const int wave = threadIdx.x >> 6;
     const int item = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + wave);
     if (item >= nitems) return;  // whole wave; the kernel has no workgroup barrier
@@ -593,7 +593,7 @@ __global__ __launch_bounds__(256) void adjoint_strip_kernel(const float *u_all, 
     s.il2 = a.inv_lam2;
     s.il3 = il3;
     s.first = first;
-    adjoint_strip_step<R, ROWS>(lds + 1 + wave * G::LDS, s, a.w, lam_partials + 2 * (size_t)item,
+    adjoint_strip_step<R, ROWS>(lds + wave * G::LDS, s, a.w, lam_partials + 2 * (size_t)item,
                                 lam_scale);
 }
 

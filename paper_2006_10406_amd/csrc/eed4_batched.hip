@@ -71,9 +71,7 @@ __global__ __launch_bounds__(256) void bstrip_kernel(const BImage *imgs, const B
                                                      StepArgs a, double *partials)
 {
     using G = StripGeo<R, ROWS>;
-    // one pad float at each end: at radius 0 the Hessian of lane 0 (63) reads
-    // one element left (right) of its ring row
-    __shared__ float lds[4 * G::LDS + 2];
+    __shared__ float lds[4 * G::LDS];
     const int wave = threadIdx.x >> 6;
     const int nw = 4 * gridDim.x;
     const int w0 = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + wave);
@@ -94,7 +92,7 @@ __global__ __launch_bounds__(256) void bstrip_kernel(const BImage *imgs, const B
         s.tau = a.tau;
         s.alpha = a.alpha;
         s.il2q = 0.25f * __int_as_float(uni(__float_as_int(d.inv_lam2)));
-        strip_step<R, RES, ROWS>(lds + 1 + wave * G::LDS, s, a.w, partials + 2 * (size_t)uni(t.slot));
+        strip_step<R, RES, ROWS>(lds + wave * G::LDS, s, a.w, partials + 2 * (size_t)uni(t.slot));
     }
 }
 

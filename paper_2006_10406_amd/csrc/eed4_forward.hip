@@ -42,9 +42,7 @@ __global__ __launch_bounds__(256) void strip_kernel(const float *ucur, const flo
                                                     double *partials)
 {
     using G = StripGeo<R, ROWS>;
-    // one pad float at each end: at radius 0 the Hessian of lane 0 (63) reads
-    // one element left (right) of its ring row
-    __shared__ float lds[4 * G::LDS + 2];
+    __shared__ float lds[4 * G::LDS];
     const int wave = threadIdx.x >> 6;
     // wave-uniform: keep the work item (and all that derives from it) in SGPRs
     const int item = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + wave);
@@ -66,7 +64,7 @@ __global__ __launch_bounds__(256) void strip_kernel(const float *ucur, const flo
     s.tau = a.tau;
     s.alpha = a.alpha;
     s.il2q = 0.25f * a.inv_lam2;
-    strip_step<R, RES, ROWS>(lds + 1 + wave * G::LDS, s, a.w,
+    strip_step<R, RES, ROWS>(lds + wave * G::LDS, s, a.w,
                              RES ? partials + 2 * (size_t)item : nullptr);
 }
 

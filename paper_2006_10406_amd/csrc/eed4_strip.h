@@ -59,6 +59,13 @@ __device__ __forceinline__ void wave_lds_sync()
 
 // ROWS is the least number of output rows of a wave's segment (the segment
 // is rounded up to whole unrolled iterations).
+//
+// The LDS ring holds the last D staged rows column-major: staged column c
+// (0 .. NU-1) of ring row r is at (c + 1) * CS + r, with an empty column on
+// each side.  A lane addresses everything it reads (x-pass taps, Hessian
+// neighbours) as compile-time offsets from its own column, which stay within
+// the reach of paired LDS reads, and the odd stride CS keeps the 64 lanes on
+// distinct banks.
 template <int R, int ROWS = 64>
 struct StripGeo {
     static constexpr int P = 2 * R + 1;                       // y window length
@@ -67,10 +74,11 @@ struct StripGeo {
     static constexpr int h = R + 2;                           // input halo
     static constexpr int SW = 60;                             // output columns per wave
     static constexpr int NU = 64 + 2 * R;                     // staged u columns per row
+    static constexpr int CS = D | 1;                          // ring column stride (odd)
     static constexpr int M = (ROWS + 4 + U - 1) / U;          // main-loop iterations
     static constexpr int NROW = 2 * R + M * U;                // rows streamed per wave
     static constexpr int OH = NROW - 2 * h;                   // output rows per wave
-    static constexpr int LDS = D * NU;                        // floats of LDS per wave
+    static constexpr int LDS = (NU + 2) * CS;                 // floats of LDS per wave
 };
 
 // Per-wave constants of a strip step.
@@ -164,8 +172,9 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
     const unsigned vo4 = out_lane ? 4u * (unsigned)cl : kOffNone;
     const unsigned vo1 = out_lane ? (unsigned)cl : kOffNone;
 
-    float *rl = ring + lane;                                  // row r of the ring at r * NU
-    float *rb = ring + 64 + lb;
+    constexpr int CS = G::CS;
+    float *col = ring + (lane + 1) * CS;                      // ring column of this lane
+    float *bcol = ring + (64 + lb + 1) * CS;                  // right-halo column it stages
 
     float win[P];             // x-pass values, row i in slot i % P
 #pragma unroll
@@ -207,13 +216,12 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
         const float a = r0.a, b = r0.b;
         r0 = r1;
         prefetch(r1);
-        rl[(i % D) * NU] = a;
-        rb[(i % D) * NU] = b;
+        col[i % D] = a;
+        bcol[i % D] = b;
         wave_lds_sync();
-        const float *slot = rl + (i % D) * NU;
-        float acc = w[0] * slot[0];
+        float acc = w[0] * col[i % D];
 #pragma unroll
-        for (int j = 1; j <= 2 * R; ++j) acc = fmaf(w[j], slot[j], acc);
+        for (int j = 1; j <= 2 * R; ++j) acc = fmaf(w[j], col[j * CS + i % D], acc);
         win[i % P] = acc;
     }
 
@@ -228,13 +236,12 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
 
             // ---- S1: stage u^k row i and take the x pass ----
             const int sr = (2 * R + ph) % D;           // a constant once unrolled
-            rl[sr * NU] = cur.a;
-            if constexpr (R > 0) rb[sr * NU] = cur.b;
+            col[sr] = cur.a;
+            if constexpr (R > 0) bcol[sr] = cur.b;
             wave_lds_sync();
-            const float *slot = rl + sr * NU;
-            float acc = w[0] * slot[0];
+            float acc = w[0] * col[sr];
 #pragma unroll
-            for (int j = 1; j <= 2 * R; ++j) acc = fmaf(w[j], slot[j], acc);
+            for (int j = 1; j <= 2 * R; ++j) acc = fmaf(w[j], col[j * CS + sr], acc);
             win[(2 * R + ph) % P] = acc;
 
             // ---- S2: y pass at stream row i - R ----
@@ -248,13 +255,14 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
             const float gys = v - v_m2;                                      // 2 gy
             v_m2 = v_m1;
             v_m1 = v;
-            const float *um = rl + ((R - 2 + ph + D) % D) * NU + R;    // row g - 1
-            const float *u0 = rl + ((R - 1 + ph + D) % D) * NU + R;    // row g
-            const float *up = rl + ((R + ph) % D) * NU + R;            // row g + 1
+            // this lane's column is staged column lane + R; rows g-1, g, g+1
+            const float *um = col + R * CS + (R - 2 + ph + D) % D;
+            const float *u0 = col + R * CS + (R - 1 + ph + D) % D;
+            const float *up = col + R * CS + (R + ph) % D;
             const float uc = u0[0];
-            const float hxx = fmaf(-2.0f, uc, u0[-1] + u0[1]);
+            const float hxx = fmaf(-2.0f, uc, u0[-CS] + u0[CS]);
             const float hyy = fmaf(-2.0f, uc, um[0] + up[0]);
-            const float hxy = 0.25f * ((up[1] + um[-1]) - (up[-1] + um[1]));
+            const float hxy = 0.25f * ((up[CS] + um[-CS]) - (up[-CS] + um[CS]));
 
             const float s2 = fmaf(gxs, gxs, gys * gys);                      // 4 |grad|^2
             const float mu1 = __builtin_amdgcn_rsqf(fmaf(s2, s.il2q, 1.0f));
