@@ -39,6 +39,21 @@ def flops_per_update(R):
     4(2R+1), gradient 2, tensor 15, Hessian 11, contraction 24, outer
     differences 13, FSI update and hold 5."""
     return 4 * (2 * R + 1) + 70
+# kernel behind each fused-step shape (template arguments: radius, residual
+# variant, least segment rows, columns per lane; or tile width and height)
+STRIP_GEOMETRY = {"strip": (64, 1), "strip_tall": (136, 1), "strip_short": (28, 1),
+                  "strip_tiny": (8, 1), "strip_wide": (64, 2), "strip_wide_short": (28, 2)}
+TILE_GEOMETRY = {"tile64x32": (64, 32), "tile64x16": (64, 16), "tile32x32": (32, 32)}
+
+
+def kernel_name(shape_name, R):
+    if shape_name in STRIP_GEOMETRY:
+        rows, cpl = STRIP_GEOMETRY[shape_name]
+        return f"strip_kernel<{R}, false, {rows}, {cpl}>"
+    tw, th = TILE_GEOMETRY[shape_name]
+    return f"step_kernel<{R}, {tw}, {th}>"
+
+
 KERNEL_SOURCES = ("paper_2006_10406_amd/csrc/eed4_strip.h",
                   "paper_2006_10406_amd/csrc/eed4_forward.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_large4096_traffic.json")
@@ -56,15 +71,15 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(updates_per_launch):
+def measured_traffic(shape_name):
     """HBM bytes per launch from the committed counter summary, or None when it
-    is missing or was taken on a different kernel source."""
+    is missing or was taken on a different kernel source or shape."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("source_sha") != kernel_source_sha():
+    if t.get("source_sha") != kernel_source_sha() or t.get("shape") != shape_name:
         return None
     return t.get("bytes_per_launch")
 
@@ -135,10 +150,16 @@ def adjoint_ratio(eed4, torch, args):
             "workload": f"adjoint16: {B} x {H}x{W}, {wl.M} cycles of {wl.n}, checkpoint per cycle"}
 
 
-def probe(eed4, torch, u_init, mask, wl):
-    """Launch the fused step 3 x n times, then copy 64 MiB device to device."""
+def probe(eed4, torch, u_init, mask, known, wl):
+    """Let the library pick the fused-step shape (one cycle of eed4_inpaint),
+    launch that step 3 x n times, then copy 64 MiB device to device."""
+    u = u_init.clone()
+    eed4.eed4_inpaint(u, mask, known, eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, 1))
+    torch.cuda.synchronize()
+    shape = eed4.eed4_step_shape(1, wl.H, wl.W, eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, 1))
+    log(f"probe: shape {eed4.SHAPE_NAMES[shape]}")
     a, b, c = u_init.clone(), u_init.clone(), u_init.clone()
-    ps = eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, 1)
+    ps = eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, 1, flags=eed4.EED4_FORCE_SHAPE(shape))
     roles = lambda k: (a, a, b) if k == 0 else ((b, a, c) if k == 1 else
                                                  ((b, c, c) if k % 2 else (c, b, b)))
     for _ in range(3):
@@ -276,7 +297,7 @@ def main():
     wsv = aligned_workspace(torch, eed4.eed4_workspace_size(eed4.EED4_OP_INPAINT, 1, H, W, pt), dev)
 
     if args.probe:
-        probe(eed4, torch, u_init, mask, wl)
+        probe(eed4, torch, u_init, mask, known, wl)
         return
 
     # ---- whole-path timing: warmup cycles, then exactly K timed cycles ----
@@ -307,7 +328,10 @@ def main():
     c = u.clone()
     e2 = torch.cuda.Event(enable_timing=True)
     e3 = torch.cuda.Event(enable_timing=True)
-    ps = eed4.params(wl.lam, wl.sigma, wl.tau, n, 1)
+    # the shape the library picked for this problem (tuned by the warmup call)
+    shape = eed4.eed4_step_shape(1, H, W, pt)
+    shape_name = eed4.SHAPE_NAMES[shape]
+    ps = eed4.params(wl.lam, wl.sigma, wl.tau, n, 1, flags=eed4.EED4_FORCE_SHAPE(shape))
     eed4.eed4_fsi_step(a, a, b, mask, ps, 0, stream=stream)  # warm
     torch.cuda.synchronize()
     def roles(k):  # same rotation as a cycle: S=a, X=b, Y=c
@@ -338,8 +362,10 @@ def main():
     R = eed4.eed4_radius(wl.sigma)
     per_launch_flops = flops_per_update(R) * H * W
     tflops = per_launch_flops / (kms * 1e-3) / 1e12
-    traffic = measured_traffic(H * W)
-    log(f"fused step kernel: {kms * 1e3:.1f} us/launch, {achieved:.0f} GB/s, {tflops:.1f} TFLOP/s")
+    traffic = measured_traffic(shape_name)
+    kname = kernel_name(shape_name, R)
+    log(f"fused step kernel {kname}: {kms * 1e3:.1f} us/launch, {achieved:.0f} GB/s, "
+        f"{tflops:.1f} TFLOP/s")
 
     out = {
         "metric": "Mpixel-updates/s of fused 4th-order EED FSI step + adjoint/forward time ratio",
@@ -357,10 +383,10 @@ def main():
         "config": {"workload": "large4096", "H": H, "W": W, "batch": 1, "sigma": wl.sigma,
                    "lambda": wl.lam, "tau": wl.tau, "cycle_len": n, "mask_density": wl.density,
                    "step": "one FSI cycle (15 fused inner steps + FP64 residual)",
-                   "parallelism": "single GPU"},
+                   "kernel_shape": shape_name, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": round(tflops, 2), "peak": round(ALU_PEAK_TFLOPS, 1),
                      "unit": "TFLOP/s", "frac": round(tflops / ALU_PEAK_TFLOPS, 4),
-                     "traffic": traffic, "kernel": "strip_kernel<6,false> (fused FSI step)",
+                     "traffic": traffic, "kernel": f"{kname} (fused FSI step)",
                      "kernel_us": round(kms * 1e3, 2),
                      "algorithmic_flops_per_launch": per_launch_flops,
                      "hbm": {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -76,7 +76,8 @@ extern "C" {
  * (the autotuner in eed4_inpaint_batched, a work-size rule elsewhere):
  * 0: 64x32 workgroup tiles, 1: 64x16 tiles, 2: 32x32 tiles, 3: wave strips of
  * 60 columns x >= 64 rows, 4: strips of >= 136 rows, 5: strips of >= 28 rows,
- * 6: strips of >= 8 rows.
+ * 6: strips of >= 8 rows, 7: strips of 124 columns (two per lane) x >= 64 rows,
+ * 8: 124-column strips of >= 28 rows.
  * All strip heights give bitwise the same results; so do all tile shapes. */
 #define EED4_FORCE_SHAPE(s)  ((((s) + 1) & 0xff) << 8)
 
@@ -196,6 +197,14 @@ int eed4_autotune_batched(const eed4_image *imgs, int B, const eed4_params *p,
                           void *ws, size_t ws_bytes, void *stream);
 
 /* Message for a return code. */
+/* Fused-step kernel shape (EED4_FORCE_SHAPE index) that eed4_inpaint,
+ * eed4_fsi_cycle and eed4_fsi_step use for B equal-size H x W images with
+ * parameters p: the forced shape, else the one the autotuner chose for this
+ * problem size in this process (eed4_inpaint tunes on first use), else the
+ * size rule used before any tuning.  No device work.  Returns the shape
+ * (>= 0) or EED4_EINVAL. */
+int eed4_step_shape(int B, int H, int W, const eed4_params *p);
+
 const char *eed4_strerror(int code);
 
 #ifdef __cplusplus

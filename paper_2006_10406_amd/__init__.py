@@ -32,7 +32,7 @@ __all__ = [
     "eed4_fsi_cycle", "eed4_fsi_step", "eed4_backward", "eed4_batched_workspace_size", "eed4_inpaint_batched",
     "eed4_strerror", "EED4_ABS_TOL", "EED4_ALLOW_LARGE_TAU", "EED4_NO_GRAPH", "EED4_TILE_KERNEL",
     "EED4_OP_INPAINT", "EED4_OP_CYCLE", "EED4_OP_BACKWARD", "EED4_FORCE_SHAPE", "SHAPE_NAMES",
-    "eed4_autotune_batched", "library_path",
+    "eed4_autotune_batched", "eed4_step_shape", "library_path",
 ]
 
 
@@ -242,6 +242,15 @@ def eed4_inpaint_batched(images, p: eed4_params, ws: Optional[torch.Tensor] = No
                                          _stream(images[0][0], stream), st)
     _check(rc, "eed4_inpaint_batched")
     return list(st)
+
+
+def eed4_step_shape(B: int, H: int, W: int, p: eed4_params) -> int:
+    """Fused-step shape id the library uses for B x H x W with p (forced, tuned
+    in this process, or the size rule); no device work."""
+    rc = _lib.lib().eed4_step_shape(B, H, W, ctypes.byref(p))
+    if rc < 0:
+        _check(rc, "eed4_step_shape")
+    return rc
 
 
 def eed4_autotune_batched(images, p: eed4_params, ws: Optional[torch.Tensor] = None,

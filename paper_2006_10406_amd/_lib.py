@@ -26,7 +26,7 @@ def EED4_FORCE_SHAPE(s):
 
 
 SHAPE_NAMES = ("tile64x32", "tile64x16", "tile32x32", "strip", "strip_tall", "strip_short",
-               "strip_tiny")
+               "strip_tiny", "strip_wide", "strip_wide_short")
 
 EED4_OP_INPAINT = 1
 EED4_OP_CYCLE = 2
@@ -35,7 +35,7 @@ EED4_OP_BACKWARD = 3
 EXPORTED = ("eed4_radius", "eed4_workspace_size", "eed4_inpaint", "eed4_fsi_cycle",
             "eed4_fsi_step",
             "eed4_backward", "eed4_batched_workspace_size", "eed4_inpaint_batched",
-            "eed4_autotune_batched", "eed4_strerror")
+            "eed4_autotune_batched", "eed4_step_shape", "eed4_strerror")
 
 
 class eed4_params(ctypes.Structure):
@@ -86,6 +86,8 @@ def lib():
                                            ctypes.POINTER(eed4_stats)]
         L.eed4_autotune_batched.restype = i
         L.eed4_autotune_batched.argtypes = [ctypes.POINTER(eed4_image), i, pp, vp, sz, vp]
+        L.eed4_step_shape.restype = i
+        L.eed4_step_shape.argtypes = [i, i, i, pp]
         L.eed4_strerror.restype = ctypes.c_char_p
         L.eed4_strerror.argtypes = [i]
         _L = L

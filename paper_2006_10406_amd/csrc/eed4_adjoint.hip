@@ -673,9 +673,11 @@ template <int R>
 static int adj_items_r(int shape, int H, int W)
 {
     switch (shape) {
-    case kShapeStrip: return adj_strip_items_t<R, 64>(H, W);
+    case kShapeStrip:
+    case kShapeStripWide: return adj_strip_items_t<R, 64>(H, W);
     case kShapeStripTall: return adj_strip_items_t<R, 136>(H, W);
-    case kShapeStripShort: return adj_strip_items_t<R, 28>(H, W);
+    case kShapeStripShort:
+    case kShapeStripWideShort: return adj_strip_items_t<R, 28>(H, W);
     case kShapeStripTiny: return adj_strip_items_t<R, 8>(H, W);
     default: return adjoint_tiles_per_image(H, W);
     }
@@ -752,9 +754,11 @@ static hipError_t launch_rev_r(const RevStep &t, const StepArgs &a, float il3, f
                                hipStream_t s)
 {
     switch (t.shape) {
-    case kShapeStrip: return launch_rev_strip<R, 64>(t, a, il3, ls, s);
+    case kShapeStrip:
+    case kShapeStripWide: return launch_rev_strip<R, 64>(t, a, il3, ls, s);
     case kShapeStripTall: return launch_rev_strip<R, 136>(t, a, il3, ls, s);
-    case kShapeStripShort: return launch_rev_strip<R, 28>(t, a, il3, ls, s);
+    case kShapeStripShort:
+    case kShapeStripWideShort: return launch_rev_strip<R, 28>(t, a, il3, ls, s);
     case kShapeStripTiny: return launch_rev_strip<R, 8>(t, a, il3, ls, s);
     default: return launch_rev_tile<R>(t, a, il3, ls, s);
     }
@@ -846,7 +850,8 @@ static std::string adjoint_tune_key(int R, int B, int H, int W)
 }
 
 // Reverse-step implementation: a forced shape (tile shapes select the tile
-// passes, strip shapes the strip kernel of that height), else the tuned
+// passes, strip shapes the strip kernel of that height; the reverse strip
+// has one column per lane), else the tuned
 // choice for this problem size, else the timing of one reverse step of each
 // on the caller's data (t holds real buffers; what it writes is scratch).
 static int adjoint_shape(const eed4_params *p, RevStep t, hipStream_t s, int *shape)
@@ -856,13 +861,14 @@ static int adjoint_shape(const eed4_params *p, RevStep t, hipStream_t s, int *sh
     if (p->flags & EED4_TILE_KERNEL) { *shape = 0; return EED4_OK; }
     const std::string key = adjoint_tune_key(t.R, t.B, t.H, t.W);
     if (tune_lookup(key, shape)) return EED4_OK;
-    const int cands[] = {0, kShapeStrip, kShapeStripTall, kShapeStripShort, kShapeStripTiny};
+    // the wide forward shapes map onto the same reverse strips as their heights
+    const int cands[] = {kShapeStrip, 0, kShapeStripTall, kShapeStripShort, kShapeStripTiny};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     const size_t N = (size_t)t.B * t.H * t.W;
     if (e == hipSuccess) e = launch_fill(t.ac, N, 0.0f, s);
-    int best = 0;
+    int best = cands[0];
     float bt = 1e30f;
     for (int c : cands) {
         if (e != hipSuccess) break;
@@ -878,7 +884,7 @@ static int adjoint_shape(const eed4_params *p, RevStep t, hipStream_t s, int *sh
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
             if (e == hipSuccess && rep > 0) tmin = std::fmin(tmin, ms);   // first run warms up
         }
-        if (e == hipSuccess && tmin < bt) {
+        if (e == hipSuccess && tmin < kTuneMargin * bt) {
             bt = tmin;
             best = c;
         }

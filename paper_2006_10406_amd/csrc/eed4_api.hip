@@ -234,6 +234,11 @@ int step_shape(const eed4_params *p, int B, int H, int W)
     const int R = eed4_radius(p->sigma);
     int shape;
     if (tune_lookup(single_tune_key(R, B, H, W), &shape)) return shape;
+    return default_step_shape(R, B, H, W);
+}
+
+int default_step_shape(int R, int B, int H, int W)
+{
     const long long waves = (long long)tiles_per_image(kShapeStrip, R, H, W) * B;
     return waves < kMinStripWaves ? 2 : kShapeStrip;
 }
@@ -252,9 +257,12 @@ int tune_single_step(const eed4_params *p, int B, int H, int W, float *S, float 
         return hip_fail(e, "event");
     }
     const StepArgs a = make_args(p->sigma, R, p->tau, p->lambda, 0);
-    int best = kShapeStrip;
+    int order[kNumShapes];
+    tune_order(default_step_shape(R, B, H, W), order);
+    int best = order[0];
     float bt = 1e30f;
-    for (int sh = 0; sh < kNumShapes && e == hipSuccess; ++sh) {
+    for (int sh : order) {
+        if (e != hipSuccess) break;
         float tmin = 1e30f;
         for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
             e = hipEventRecord(e0, s);
@@ -265,7 +273,7 @@ int tune_single_step(const eed4_params *p, int B, int H, int W, float *S, float 
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
             if (e == hipSuccess && rep > 0) tmin = std::fmin(tmin, ms);   // first run warms up
         }
-        if (e == hipSuccess && tmin < bt) {
+        if (e == hipSuccess && tmin < kTuneMargin * bt) {
             bt = tmin;
             best = sh;
         }
@@ -289,6 +297,12 @@ int check_ws(void *ws, size_t ws_bytes, size_t need)
 using namespace eed4;
 
 extern "C" {
+
+int eed4_step_shape(int B, int H, int W, const eed4_params *p)
+{
+    const int rc = check_params(p, B, H, W);
+    return rc != EED4_OK ? rc : step_shape(p, B, H, W);
+}
 
 int eed4_radius(float sigma)
 {

@@ -65,12 +65,12 @@ __device__ __forceinline__ T *uni(T *p)
 
 // Wave-strip shapes: wave w of the launch takes items w, w + nw, w + 2 nw, ...
 // (w counted in XCD-contiguous order).
-template <int R, int ROWS, bool RES>
+template <int R, int ROWS, bool RES, int CPL>
 __global__ __launch_bounds__(256) void bstrip_kernel(const BImage *imgs, const BItem *queue,
                                                      const int *qlen_p, int sc, int sp, int so,
                                                      StepArgs a, double *partials)
 {
-    using G = StripGeo<R, ROWS>;
+    using G = StripGeo<R, ROWS, CPL>;
     __shared__ float lds[4 * G::LDS];
     const int wave = threadIdx.x >> 6;
     const int nw = 4 * gridDim.x;
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256) void bstrip_kernel(const BImage *imgs, const B
         s.tau = a.tau;
         s.alpha = a.alpha;
         s.il2q = 0.25f * __int_as_float(uni(__float_as_int(d.inv_lam2)));
-        strip_step<R, RES, ROWS>(lds + wave * G::LDS, s, a.w, partials + 2 * (size_t)uni(t.slot));
+        strip_step<R, RES, ROWS, CPL>(lds + wave * G::LDS, s, a.w, partials + 2 * (size_t)uni(t.slot));
     }
 }
 
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(256) void bhold_kernel(float *u, const uint8_t *__r
 static void item_dims(int shape, int R, int *iw, int *ih)
 {
     if (is_strip(shape)) {
-        *iw = StripGeo<0>::SW;
+        *iw = strip_width(shape);
         *ih = strip_rows(R, shape);
         return;
     }
@@ -195,21 +195,23 @@ static hipError_t launch_bstep_r(int shape, int grid, const BImage *imgs, const 
 #define EED4_BTILE(TW, TH)                                                                    \
     hipLaunchKernelGGL((btile_kernel<R, TW, TH>), g, b, 0, s, imgs, queue, qlen, sc, sp, so, \
                        res ? 1 : 0, a, partials)
-#define EED4_BSTRIP(ROWS)                                                                    \
-    if (res)                                                                                 \
-        hipLaunchKernelGGL((bstrip_kernel<R, ROWS, true>), g, b, 0, s, imgs, queue, qlen, sc, \
-                           sp, so, a, partials);                                             \
-    else                                                                                     \
-        hipLaunchKernelGGL((bstrip_kernel<R, ROWS, false>), g, b, 0, s, imgs, queue, qlen,   \
-                           sc, sp, so, a, partials)
+#define EED4_BSTRIP(ROWS, CPL)                                                           \
+    if (res)                                                                             \
+        hipLaunchKernelGGL((bstrip_kernel<R, ROWS, true, CPL>), g, b, 0, s, imgs, queue, \
+                           qlen, sc, sp, so, a, partials);                               \
+    else                                                                                 \
+        hipLaunchKernelGGL((bstrip_kernel<R, ROWS, false, CPL>), g, b, 0, s, imgs, queue, \
+                           qlen, sc, sp, so, a, partials)
     switch (shape) {
     case 0: EED4_BTILE(64, 32); break;
     case 1: EED4_BTILE(64, 16); break;
     case 2: EED4_BTILE(32, 32); break;
-    case kShapeStrip: EED4_BSTRIP(64); break;
-    case kShapeStripTall: EED4_BSTRIP(136); break;
-    case kShapeStripShort: EED4_BSTRIP(28); break;
-    case kShapeStripTiny: EED4_BSTRIP(8); break;
+    case kShapeStrip: EED4_BSTRIP(64, 1); break;
+    case kShapeStripTall: EED4_BSTRIP(136, 1); break;
+    case kShapeStripShort: EED4_BSTRIP(28, 1); break;
+    case kShapeStripTiny: EED4_BSTRIP(8, 1); break;
+    case kShapeStripWide: EED4_BSTRIP(64, 2); break;
+    case kShapeStripWideShort: EED4_BSTRIP(28, 2); break;
     default: return hipErrorInvalidValue;
     }
 #undef EED4_BTILE
@@ -433,9 +435,12 @@ static int autotune(const eed4_image *im, int B, const eed4_params *p, char *bas
         (void)hipEventDestroy(e0);
         return hip_fail(hipErrorInvalidValue, "event");
     }
+    int order[kNumShapes];
+    tune_order(kShapeStrip, order);
     int best = kShapeStrip, rc = EED4_OK;
     float bt = 1e30f;
-    for (int sh = 0; sh < kNumShapes && rc == EED4_OK; ++sh) {
+    for (int sh : order) {
+        if (rc != EED4_OK) break;
         BatchRun r;
         if ((rc = prepare(r, im, B, p, sh, base, L, s)) != EED4_OK) break;
         StepArgs a = make_args(p->sigma, r.R, p->tau, 1.0f, 0);
@@ -452,7 +457,7 @@ static int autotune(const eed4_image *im, int B, const eed4_params *p, char *bas
             if (e != hipSuccess) rc = hip_fail(e, "autotune timing");
             else if (rep > 0) tmin = std::min(tmin, ms);   // first run warms up
         }
-        if (rc == EED4_OK && tmin < bt) {
+        if (rc == EED4_OK && tmin < kTuneMargin * bt) {
             bt = tmin;
             best = sh;
         }

@@ -34,14 +34,14 @@ __global__ __launch_bounds__(256) void step_kernel(const float *ucur, const floa
                          partials ? partials + 2 * (size_t)tile : nullptr);
 }
 
-template <int R, bool RES, int ROWS>
+template <int R, bool RES, int ROWS, int CPL>
 __global__ __launch_bounds__(256) void strip_kernel(const float *ucur, const float *uprev,
                                                     float *uout, const float *ref,
                                                     const uint8_t *__restrict__ mask, int H, int W,
                                                     int nstrip, int per_img, int nitems, StepArgs a,
                                                     double *partials)
 {
-    using G = StripGeo<R, ROWS>;
+    using G = StripGeo<R, ROWS, CPL>;
     __shared__ float lds[4 * G::LDS];
     const int wave = threadIdx.x >> 6;
     // wave-uniform: keep the work item (and all that derives from it) in SGPRs
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void strip_kernel(const float *ucur, const flo
     s.tau = a.tau;
     s.alpha = a.alpha;
     s.il2q = 0.25f * a.inv_lam2;
-    strip_step<R, RES, ROWS>(lds + wave * G::LDS, s, a.w,
+    strip_step<R, RES, ROWS, CPL>(lds + wave * G::LDS, s, a.w,
                              RES ? partials + 2 * (size_t)item : nullptr);
 }
 
@@ -113,6 +113,8 @@ static int strip_oh(int shape)
     case kShapeStripTall: return StripGeo<R, 136>::OH;
     case kShapeStripShort: return StripGeo<R, 28>::OH;
     case kShapeStripTiny: return StripGeo<R, 8>::OH;
+    case kShapeStripWideShort: return StripGeo<R, 28, 2>::OH;
+    case kShapeStripWide: return StripGeo<R, 64, 2>::OH;
     default: return StripGeo<R, 64>::OH;
     }
 }
@@ -131,7 +133,7 @@ int strip_rows(int R, int shape)
 int tiles_per_image(int shape, int R, int H, int W)
 {
     if (is_strip(shape)) {
-        const int oh = strip_rows(R, shape), sw = StripGeo<0>::SW;
+        const int oh = strip_rows(R, shape), sw = strip_width(shape);
         if (oh <= 0) return 0;
         return ((W + sw - 1) / sw) * ((H + oh - 1) / oh);
     }
@@ -139,22 +141,22 @@ int tiles_per_image(int shape, int R, int H, int W)
     return ((W + ts.tw - 1) / ts.tw) * ((H + ts.th - 1) / ts.th);
 }
 
-template <int R, int ROWS>
+template <int R, int ROWS, int CPL = 1>
 static hipError_t launch_strip_t(const float *ucur, const float *uprev, float *uout,
                                  const float *ref, const uint8_t *mask, int B, int H, int W,
                                  const StepArgs &a, double *partials, hipStream_t s)
 {
-    using G = StripGeo<R, ROWS>;
+    using G = StripGeo<R, ROWS, CPL>;
     const int nstrip = (W + G::SW - 1) / G::SW;
     const int per_img = nstrip * ((H + G::OH - 1) / G::OH);
     const long long nitems = (long long)per_img * B;
     const long long nblk = (nitems + 3) / 4;
     if (nitems <= 0 || nblk > 0x7fffffffLL) return hipErrorInvalidValue;
     if (ref)
-        hipLaunchKernelGGL((strip_kernel<R, true, ROWS>), dim3((unsigned)nblk), dim3(256), 0, s, ucur,
+        hipLaunchKernelGGL((strip_kernel<R, true, ROWS, CPL>), dim3((unsigned)nblk), dim3(256), 0, s, ucur,
                            uprev, uout, ref, mask, H, W, nstrip, per_img, (int)nitems, a, partials);
     else
-        hipLaunchKernelGGL((strip_kernel<R, false, ROWS>), dim3((unsigned)nblk), dim3(256), 0, s, ucur,
+        hipLaunchKernelGGL((strip_kernel<R, false, ROWS, CPL>), dim3((unsigned)nblk), dim3(256), 0, s, ucur,
                            uprev, uout, ref, mask, H, W, nstrip, per_img, (int)nitems, a, partials);
     return hipGetLastError();
 }
@@ -186,6 +188,8 @@ static hipError_t launch_step_r(int shape, const float *ucur, const float *uprev
     case kShapeStripTall: return launch_strip_t<R, 136>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
     case kShapeStripShort: return launch_strip_t<R, 28>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
     case kShapeStripTiny: return launch_strip_t<R, 8>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
+    case kShapeStripWide: return launch_strip_t<R, 64, 2>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
+    case kShapeStripWideShort: return launch_strip_t<R, 28, 2>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -30,6 +30,20 @@ int step_shape(const eed4_params *p, int B, int H, int W);
 // chip), and strips otherwise.
 constexpr long long kMinStripWaves = 2048;
 
+// The autotuners time the default shape first and move to another only when
+// it is faster by more than this factor, so shapes within timing noise of each
+// other do not swap between runs.
+constexpr float kTuneMargin = 0.98f;
+// Candidate order for a tuner: `first`, then the other shapes in index order.
+inline void tune_order(int first, int (&order)[kNumShapes])
+{
+    int n = 0;
+    order[n++] = first;
+    for (int sh = 0; sh < kNumShapes; ++sh)
+        if (sh != first) order[n++] = sh;
+}
+int default_step_shape(int R, int B, int H, int W);
+
 // Autotuner choice cache (process-wide; persisted to the file named by
 // EED4_AUTOTUNE_CACHE when set).
 bool tune_lookup(const std::string &key, int *shape);

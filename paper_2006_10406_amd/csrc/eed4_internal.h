@@ -25,23 +25,27 @@ struct TileShape {
 };
 
 // Kernel shapes compiled into the library (index = config id): 0..2 are
-// workgroup tiles (tw x th outputs per 256-thread workgroup); 3..6 are
-// wave strips (60 columns x a segment of rows per wave).
+// workgroup tiles (tw x th outputs per 256-thread workgroup); 3..8 are
+// wave strips (60 or 124 columns x a segment of rows per wave).
 constexpr int kNumTileShapes = 3;
 constexpr TileShape kTileShapes[kNumTileShapes] = {{64, 32}, {64, 16}, {32, 32}};
 constexpr int kShapeStrip = 3;       // wave strips of >= 64 output rows
 constexpr int kShapeStripTall = 4;   // >= 136 rows
 constexpr int kShapeStripShort = 5;  // >= 28 rows (more waves for small images)
 constexpr int kShapeStripTiny = 6;   // >= 8 rows (shortest row pipeline per wave)
-constexpr int kNumShapes = 7;
+constexpr int kShapeStripWide = 7;       // two columns per lane (124 per wave), >= 64 rows
+constexpr int kShapeStripWideShort = 8;  // two columns per lane, >= 28 rows
+constexpr int kNumShapes = 9;
 constexpr bool is_strip(int shape) { return shape >= kShapeStrip && shape < kNumShapes; }
 constexpr int strip_target_rows(int shape)
 {
     return shape == kShapeStripTall ? 136
-         : shape == kShapeStripShort ? 28
+         : shape == kShapeStripShort || shape == kShapeStripWideShort ? 28
          : shape == kShapeStripTiny  ? 8
                                      : 64;
 }
+constexpr int strip_cols_per_lane(int shape) { return shape >= kShapeStripWide ? 2 : 1; }
+constexpr int strip_width(int shape) { return 64 * strip_cols_per_lane(shape) - 4; }
 
 // ---- launchers (eed4_forward.hip) ----
 hipError_t launch_hold(float *u, const uint8_t *mask, const float *known, size_t n,

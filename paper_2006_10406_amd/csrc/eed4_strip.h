@@ -1,21 +1,24 @@
 // Device code of one fused FOEED/FSI inner step on a vertical strip, one
 // wavefront per strip, no workgroup barriers.
 //
-// A wave owns 64 consecutive columns c = X0-2 .. X0+61 (one per lane) and
-// streams down the rows of a segment.  For each input row y it
-//   S1  stages u^k(y, X0-2-R .. X0+61+R) in a per-wave LDS ring (mirrored
+// A wave owns NL = 64 CPL consecutive columns c = X0-2 .. X0+NL-3 (CPL
+// adjacent columns per lane) and streams down the rows of a segment.  For
+// each input row y it
+//   S1  stages u^k(y, X0-2-R .. X0+NL-3+R) in a per-wave LDS ring (mirrored
 //       indices realise the Neumann condition, Sec. 2.1) and takes the x pass
-//       of the Gaussian presmoothing (Sec. 2.2) at its column;
+//       of the Gaussian presmoothing (Sec. 2.2) at its columns;
 //   S2  completes the y pass at row y-R from a register window of the last
 //       2R+1 x-pass values (the row loop is unrolled over that window);
-//   S3  at row g = y-R-1: central-difference gradient of u_sigma (lane
-//       neighbours through DPP wave shifts), fourth-order diffusion tensor
-//       (Sec. 3.1: eigenvalues g, 1, sqrt g), Hessian of u from the LDS ring
-//       (Sec. 3.3 stencils, sign-corrected u_xy) and T = D : H;
+//   S3  at row g = y-R-1: central-difference gradient of u_sigma, fourth-order
+//       diffusion tensor (Sec. 3.1: eigenvalues g, 1, sqrt g), Hessian of u
+//       from the LDS ring (Sec. 3.3 stencils, sign-corrected u_xy) and
+//       T = D : H;
 //   S4  at row o = g-1: outer differences of T (eq. genModel), explicit step,
 //       FSI extrapolation (Sec. 3.3), Dirichlet hold; optional FP64 residual.
-// Outputs are the 60 columns X0 .. X0+59 (lanes 2..61).  Every intermediate
-// lives on the mirror-extended image, so P stays symmetric.
+// Horizontal neighbours inside a lane are its own registers; across lanes
+// they come from DPP wave shifts.  Outputs are the NL-4 columns X0 ..
+// X0+NL-5.  Every intermediate lives on the mirror-extended image, so P stays
+// symmetric, and each pixel's arithmetic is the same for every CPL.
 #pragma once
 
 #include "eed4_internal.h"
@@ -66,14 +69,15 @@ __device__ __forceinline__ void wave_lds_sync()
 // neighbours) as compile-time offsets from its own column, which stay within
 // the reach of paired LDS reads, and the odd stride CS keeps the 64 lanes on
 // distinct banks.
-template <int R, int ROWS = 64>
+template <int R, int ROWS = 64, int CPL = 1>
 struct StripGeo {
     static constexpr int P = 2 * R + 1;                       // y window length
     static constexpr int U = P * ((R + 3 + P - 1) / P);       // unroll = LDS ring depth
     static constexpr int D = U;                               // (a multiple of P, >= R+3)
     static constexpr int h = R + 2;                           // input halo
-    static constexpr int SW = 60;                             // output columns per wave
-    static constexpr int NU = 64 + 2 * R;                     // staged u columns per row
+    static constexpr int NL = 64 * CPL;                       // columns held by the lanes
+    static constexpr int SW = NL - 4;                         // output columns per wave
+    static constexpr int NU = NL + 2 * R;                     // staged u columns per row
     static constexpr int CS = D | 1;                          // ring column stride (odd)
     static constexpr int M = (ROWS + 4 + U - 1) / U;          // main-loop iterations
     static constexpr int NROW = 2 * R + M * U;                // rows streamed per wave
@@ -127,24 +131,38 @@ struct RowTrack {
     }
 };
 
-// Global loads of one stream row: u^k of the row itself, and u^{k-1}, the
-// mask and the residual reference of the output row it serves.
+// Global loads of one stream row: u^k of the row itself (the lane's columns
+// and one right-halo column), and u^{k-1}, the mask and the residual
+// reference of the output row it serves.
+template <int CPL>
 struct StripRow {
-    float a, b, pv, rf;
-    unsigned mk;
+    float a[CPL], b, pv[CPL], rf[CPL];
+    unsigned mk[CPL];
 };
+
+// Column q's left / right neighbour of a per-column register quantity.
+template <int CPL>
+__device__ __forceinline__ float left_of(const float (&x)[CPL], int q)
+{
+    return q > 0 ? x[q - 1] : from_prev_lane(x[CPL - 1]);
+}
+template <int CPL>
+__device__ __forceinline__ float right_of(const float (&x)[CPL], int q)
+{
+    return q < CPL - 1 ? x[q + 1] : from_next_lane(x[0]);
+}
 
 // Addressing: every plane is seen through a buffer resource based at image
 // row b0 = max(Y0 - h, 0) (the lowest row a needed value comes from) and
 // covering nb = min(H - b0, NROW) rows, so a row offset is one 32-bit scalar
 // (the library keeps NROW * W * 4 below 2^31) and the per-lane column offsets
 // stay fixed for the whole strip.
-template <int R, bool RES, int ROWS = 64>
+template <int R, bool RES, int ROWS = 64, int CPL = 1>
 __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
                                            const float (&w)[2 * kRMax + 1], double *partial)
 {
-    using G = StripGeo<R, ROWS>;
-    constexpr int P = G::P, U = G::U, D = G::D, NU = G::NU;
+    using G = StripGeo<R, ROWS, CPL>;
+    constexpr int P = G::P, U = G::U, D = G::D, NL = G::NL, CS = G::CS;
     const int lane = threadIdx.x & 63;
     const int H = s.H, W = s.W;
     const unsigned W4 = 4u * (unsigned)W;
@@ -160,29 +178,38 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
     __amdgpu_buffer_rsrc_t rs_r = rs_p;
     if constexpr (RES) rs_r = buffer_rsrc(s.ref + base, (unsigned)nb * W4);
 
-    // staged columns (fixed for the whole strip): lane l stages column
-    // X0-2-R+l at ring position l, and the 2R right-halo columns X0+62-R..
-    // at positions 64..63+2R, lane l writing position 64 + l mod 2R (lanes
-    // with the same position load and write the same value)
-    const unsigned ca = 4u * (unsigned)mirror_reflect(s.X0 - 2 - R + lane, W);
+    // Staged columns (fixed for the whole strip): staged column j is image
+    // column X0-2-R+j.  Lane l stages j = CPL l + q (q < CPL), and the 2R
+    // right-halo columns j = NL .. NL+2R-1 go to lane l = j - NL mod 2R
+    // (lanes with the same halo column load and write the same value).
     const int lb = R > 0 ? lane % (2 * R > 0 ? 2 * R : 1) : 0;
-    const unsigned cb = 4u * (unsigned)mirror_reflect(s.X0 + 62 - R + lb, W);
-    const int cl = s.X0 - 2 + lane;                           // this lane's column
-    const bool out_lane = lane >= 2 && lane < 62 && cl < W;
-    const unsigned vo4 = out_lane ? 4u * (unsigned)cl : kOffNone;
-    const unsigned vo1 = out_lane ? (unsigned)cl : kOffNone;
-
-    constexpr int CS = G::CS;
-    float *col = ring + (lane + 1) * CS;                      // ring column of this lane
-    float *bcol = ring + (64 + lb + 1) * CS;                  // right-halo column it stages
-
-    float win[P];             // x-pass values, row i in slot i % P
+    const unsigned cb = 4u * (unsigned)mirror_reflect(s.X0 - 2 - R + NL + lb, W);
+    unsigned ca[CPL], vo4[CPL], vo1[CPL];
+    bool out_col[CPL];
 #pragma unroll
-    for (int j = 0; j < P; ++j) win[j] = 0.0f;
-    float v_m1 = 0.0f, v_m2 = 0.0f;                      // v at rows g, g-1 (before update)
-    float txx_p = 0.0f, tyy_p = 0.0f, tyy_pp = 0.0f;     // T at rows g-1 (and g-2 for Tyy)
-    float z_p = 0.0f, z_pp = 0.0f;                       // Txy(l+1)-Txy(l-1) at rows g-1, g-2
-    float uc_p = 0.0f;                                   // u^k(g-1, c)
+    for (int q = 0; q < CPL; ++q) {
+        const int j = CPL * lane + q;                        // this column, within the wave
+        const int cl = s.X0 - 2 + j;                         // ... and in the image
+        ca[q] = 4u * (unsigned)mirror_reflect(cl - R, W);
+        out_col[q] = j >= 2 && j < NL - 2 && cl < W;
+        vo4[q] = out_col[q] ? 4u * (unsigned)cl : kOffNone;
+        vo1[q] = out_col[q] ? (unsigned)cl : kOffNone;
+    }
+    float *col = ring + (CPL * lane + 1) * CS;               // ring column of staged column CPL l
+    float *bcol = ring + (NL + lb + 1) * CS;                 // right-halo column it stages
+
+    float win[CPL][P];        // x-pass values, row i in slot i % P
+#pragma unroll
+    for (int q = 0; q < CPL; ++q)
+#pragma unroll
+        for (int j = 0; j < P; ++j) win[q][j] = 0.0f;
+    float v_m1[CPL], v_m2[CPL];                          // v at rows g, g-1 (before update)
+    float txx_p[CPL], tyy_p[CPL], tyy_pp[CPL];           // T at rows g-1 (and g-2 for Tyy)
+    float z_p[CPL], z_pp[CPL];                           // Txy(c+1)-Txy(c-1) at rows g-1, g-2
+    float uc_p[CPL];                                     // u^k(g-1, c)
+#pragma unroll
+    for (int q = 0; q < CPL; ++q)
+        v_m1[q] = v_m2[q] = txx_p[q] = tyy_p[q] = tyy_pp[q] = z_p[q] = z_pp[q] = uc_p[q] = 0.0f;
     double d2 = 0.0, n2 = 0.0;
 
     // the next row to prefetch: its mirrored image row and the output row it serves
@@ -192,37 +219,52 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
 
     // Loads run two stream rows ahead, always in the same order, so waiting
     // for one row never waits for a later row's loads.
-    auto prefetch = [&](StripRow &r) {
+    auto prefetch = [&](StripRow<CPL> &r) {
         const unsigned su = (unsigned)((ty.y > b0 ? ty.y : b0) - b0) * W4;
-        r.a = buf_f32(rs_u, ca, su);
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) r.a[q] = buf_f32(rs_u, ca[q], su);
         if constexpr (R > 0) r.b = buf_f32(rs_u, cb, su);
         int oc = on < b0 ? b0 : on;                      // clamped; unused rows are not stored
         oc = oc > H - 1 ? H - 1 : oc;
         const unsigned ro = (unsigned)(oc - b0);
-        r.pv = buf_f32(rs_p, vo4, ro * W4);
-        r.mk = __builtin_amdgcn_raw_buffer_load_b8(rs_m, vo1, ro * (unsigned)W, 0);
-        if constexpr (RES) r.rf = buf_f32(rs_r, vo4, ro * W4);
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) {
+            r.pv[q] = buf_f32(rs_p, vo4[q], ro * W4);
+            r.mk[q] = __builtin_amdgcn_raw_buffer_load_b8(rs_m, vo1[q], ro * (unsigned)W, 0);
+            if constexpr (RES) r.rf[q] = buf_f32(rs_r, vo4[q], ro * W4);
+        }
         ty.next(H);
         ++on;
     };
-    StripRow r0, r1;
-    r0.b = r1.b = r0.rf = r1.rf = 0.0f;
+    StripRow<CPL> r0, r1;
+    r0.b = r1.b = 0.0f;
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) r0.rf[q] = r1.rf[q] = 0.0f;
     prefetch(r0);
     prefetch(r1);
+
+    // stage one row of u^k into ring row rr and take its x pass into window slot ws
+    auto stage_xpass = [&](const StripRow<CPL> &cur, int rr, int ws) {
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) col[q * CS + rr] = cur.a[q];
+        if constexpr (R > 0) bcol[rr] = cur.b;
+        wave_lds_sync();
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) {
+            float acc = w[0] * col[q * CS + rr];
+#pragma unroll
+            for (int j = 1; j <= 2 * R; ++j) acc = fmaf(w[j], col[(q + j) * CS + rr], acc);
+            win[q][ws] = acc;
+        }
+    };
 
     // ---- prologue: stage rows 0 .. 2R-1 and their x pass ----
 #pragma unroll
     for (int i = 0; i < 2 * R; ++i) {
-        const float a = r0.a, b = r0.b;
+        const StripRow<CPL> cur = r0;
         r0 = r1;
         prefetch(r1);
-        col[i % D] = a;
-        bcol[i % D] = b;
-        wave_lds_sync();
-        float acc = w[0] * col[i % D];
-#pragma unroll
-        for (int j = 1; j <= 2 * R; ++j) acc = fmaf(w[j], col[j * CS + i % D], acc);
-        win[i % P] = acc;
+        stage_xpass(cur, i % D, i % P);
     }
 
 #pragma unroll 1
@@ -230,82 +272,94 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
 #pragma unroll
         for (int ph = 0; ph < U; ++ph) {
             const int i = 2 * R + it * U + ph;           // stream row (wave-uniform)
-            const StripRow cur = r0;
+            const StripRow<CPL> cur = r0;
             r0 = r1;
             prefetch(r1);                                 // mirrored: always valid rows
 
             // ---- S1: stage u^k row i and take the x pass ----
-            const int sr = (2 * R + ph) % D;           // a constant once unrolled
-            col[sr] = cur.a;
-            if constexpr (R > 0) bcol[sr] = cur.b;
-            wave_lds_sync();
-            float acc = w[0] * col[sr];
-#pragma unroll
-            for (int j = 1; j <= 2 * R; ++j) acc = fmaf(w[j], col[j * CS + sr], acc);
-            win[(2 * R + ph) % P] = acc;
+            stage_xpass(cur, (2 * R + ph) % D, (2 * R + ph) % P);   // constants once unrolled
 
             // ---- S2: y pass at stream row i - R ----
-            float v = w[0] * win[ph % P];
+            float v[CPL];
 #pragma unroll
-            for (int j = 1; j <= 2 * R; ++j) v = fmaf(w[j], win[(ph + j) % P], v);
+            for (int q = 0; q < CPL; ++q) {
+                v[q] = w[0] * win[q][ph % P];
+#pragma unroll
+                for (int j = 1; j <= 2 * R; ++j) v[q] = fmaf(w[j], win[q][(ph + j) % P], v[q]);
+            }
 
             // ---- S3: gradient, tensor, Hessian, contraction at row g = i - R - 1 ----
             // (the first rows of the loop produce values that only feed unstored rows)
-            const float gxs = from_next_lane(v_m1) - from_prev_lane(v_m1);  // 2 gx
-            const float gys = v - v_m2;                                      // 2 gy
-            v_m2 = v_m1;
-            v_m1 = v;
-            // this lane's column is staged column lane + R; rows g-1, g, g+1
-            const float *um = col + R * CS + (R - 2 + ph + D) % D;
-            const float *u0 = col + R * CS + (R - 1 + ph + D) % D;
-            const float *up = col + R * CS + (R + ph) % D;
-            const float uc = u0[0];
-            const float hxx = fmaf(-2.0f, uc, u0[-CS] + u0[CS]);
-            const float hyy = fmaf(-2.0f, uc, um[0] + up[0]);
-            const float hxy = 0.25f * ((up[CS] + um[-CS]) - (up[-CS] + um[CS]));
+            float txx[CPL], tyy[CPL], txy[CPL], uc[CPL];
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) {
+                const float gxs = right_of(v_m1, q) - left_of(v_m1, q);      // 2 gx
+                const float gys = v[q] - v_m2[q];                             // 2 gy
+                // column q of this lane is staged column CPL l + q + R; rows g-1, g, g+1
+                const float *um = col + (q + R) * CS + (R - 2 + ph + D) % D;
+                const float *u0 = col + (q + R) * CS + (R - 1 + ph + D) % D;
+                const float *up = col + (q + R) * CS + (R + ph) % D;
+                uc[q] = u0[0];
+                const float hxx = fmaf(-2.0f, uc[q], u0[-CS] + u0[CS]);
+                const float hyy = fmaf(-2.0f, uc[q], um[0] + up[0]);
+                const float hxy = 0.25f * ((up[CS] + um[-CS]) - (up[-CS] + um[CS]));
 
-            const float s2 = fmaf(gxs, gxs, gys * gys);                      // 4 |grad|^2
-            const float mu1 = __builtin_amdgcn_rsqf(fmaf(s2, s.il2q, 1.0f));
-            const float mu3 = __builtin_amdgcn_sqrtf(mu1);
-            const float rn = __builtin_amdgcn_rsqf(fmaxf(s2, 1e-30f));
-            const float nx = gxs * rn, ny = gys * rn;   // unit direction (0 where grad = 0)
-            const float aa = nx * nx, bb = ny * ny, c = nx * ny;
-            const float amb = aa - bb, c2 = c + c;
-            const float e1h = fmaf(aa, hxx, fmaf(bb, hyy, c2 * hxy));
-            const float x3 = fmaf(c, hyy - hxx, amb * hxy);
-            const float k1 = fmaf(mu1, e1h, -e1h);
-            const float k3 = fmaf(mu3, x3, -x3);
-            const float k3c2 = k3 * c2;
-            const float txx = fmaf(k1, aa, hxx - k3c2);
-            const float tyy = fmaf(k1, bb, hyy + k3c2);
-            const float txy = fmaf(k1, c, fmaf(k3, amb, hxy));
-            const float z = from_next_lane(txy) - from_prev_lane(txy);
+                const float s2 = fmaf(gxs, gxs, gys * gys);                  // 4 |grad|^2
+                const float mu1 = __builtin_amdgcn_rsqf(fmaf(s2, s.il2q, 1.0f));
+                const float mu3 = __builtin_amdgcn_sqrtf(mu1);
+                const float rn = __builtin_amdgcn_rsqf(fmaxf(s2, 1e-30f));
+                const float nx = gxs * rn, ny = gys * rn;   // unit direction (0 where grad = 0)
+                const float aa = nx * nx, bb = ny * ny, c = nx * ny;
+                const float amb = aa - bb, c2 = c + c;
+                const float e1h = fmaf(aa, hxx, fmaf(bb, hyy, c2 * hxy));
+                const float x3 = fmaf(c, hyy - hxx, amb * hxy);
+                const float k1 = fmaf(mu1, e1h, -e1h);
+                const float k3 = fmaf(mu3, x3, -x3);
+                const float k3c2 = k3 * c2;
+                txx[q] = fmaf(k1, aa, hxx - k3c2);
+                tyy[q] = fmaf(k1, bb, hyy + k3c2);
+                txy[q] = fmaf(k1, c, fmaf(k3, amb, hxy));
+            }
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) {
+                v_m2[q] = v_m1[q];
+                v_m1[q] = v[q];
+            }
 
             // ---- S4: output row o = g - 1 (stream row i - R - 2) ----
+            float z[CPL];
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) z[q] = right_of(txy, q) - left_of(txy, q);
             const int o = ybase + i - R - 2;
             if (i >= 2 * G::h && o < H) {      // first output row of the segment is Y0
-                const float sxx = from_prev_lane(txx_p) + from_next_lane(txx_p);
-                const float pu = fmaf(-2.0f, txx_p + tyy_p, sxx + (tyy_pp + tyy)) +
-                                 0.5f * (z - z_pp);
-                const float wv = fmaf(-s.tau, pu, uc_p);
-                float un = fmaf(s.alpha, wv - cur.pv, cur.pv);
-                if (cur.mk) un = uc_p;
-                if constexpr (RES) {
-                    // lanes without a pixel read 0 for the reference; add 0
-                    const double du = out_lane ? (double)un : 0.0;
-                    const double dd = du - (double)cur.rf;
-                    d2 = fma(dd, dd, d2);
-                    n2 = fma(du, du, n2);
+                const unsigned ro = (unsigned)(o - b0) * W4;
+#pragma unroll
+                for (int q = 0; q < CPL; ++q) {
+                    const float sxx = left_of(txx_p, q) + right_of(txx_p, q);
+                    const float pu = fmaf(-2.0f, txx_p[q] + tyy_p[q], sxx + (tyy_pp[q] + tyy[q])) +
+                                     0.5f * (z[q] - z_pp[q]);
+                    const float wv = fmaf(-s.tau, pu, uc_p[q]);
+                    float un = fmaf(s.alpha, wv - cur.pv[q], cur.pv[q]);
+                    if (cur.mk[q]) un = uc_p[q];
+                    if constexpr (RES) {
+                        // columns without a pixel read 0 for the reference; add 0
+                        const double du = out_col[q] ? (double)un : 0.0;
+                        const double dd = du - (double)cur.rf[q];
+                        d2 = fma(dd, dd, d2);
+                        n2 = fma(du, du, n2);
+                    }
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(un), rs_o, vo4[q], ro, 0);
                 }
-                const unsigned ro = (unsigned)(o - b0);
-                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(un), rs_o, vo4, ro * W4, 0);
             }
-            tyy_pp = tyy_p;
-            tyy_p = tyy;
-            txx_p = txx;
-            z_pp = z_p;
-            z_p = z;
-            uc_p = uc;
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) {
+                tyy_pp[q] = tyy_p[q];
+                tyy_p[q] = tyy[q];
+                txx_p[q] = txx[q];
+                z_pp[q] = z_p[q];
+                z_p[q] = z[q];
+                uc_p[q] = uc[q];
+            }
         }
     }
     if constexpr (RES) {

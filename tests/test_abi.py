@@ -89,6 +89,22 @@ def test_argument_errors_before_any_gpu_work(lib):
     assert _call_inpaint(lib, big, ws=0) == e._lib.EED4_EWORKSPACE
 
 
+def test_step_shape_query_without_tuning(lib):
+    # no device work: forced shapes, the tile flag and the size rule used
+    # before any tuning (strips when they give enough waves, else 32x32 tiles)
+    import ctypes
+    import paper_2006_10406_amd as e
+    q = lambda B, H, W, p: lib.eed4_step_shape(B, H, W, ctypes.byref(p))
+    for sh in range(len(e.SHAPE_NAMES)):
+        assert q(1, 300, 200, e.params(0.05, 1.0, 0.05, 10, 2, flags=e.EED4_FORCE_SHAPE(sh))) == sh
+    assert q(1, 300, 200, e.params(0.05, 1.0, 0.05, 10, 2, flags=e.EED4_TILE_KERNEL)) == 0
+    assert q(1, 4096, 4096, e.params(0.02, 2.0, 0.05, 15, 2)) == 3
+    assert q(1, 64, 64, e.params(0.05, 1.0, 0.05, 10, 2)) == 2
+    assert q(1, 0, 64, e.params(0.05, 1.0, 0.05, 10, 2)) == e._lib.EED4_EINVAL
+    assert q(1, 64, 64, e.params(0.05, 1.0, 0.05, 10, 2, flags=e.EED4_FORCE_SHAPE(99))) == \
+        e._lib.EED4_EINVAL
+
+
 def test_strerror(lib):
     import paper_2006_10406_amd as e
     for c in (0, -1, -2, -3, -4, -5, 7):
