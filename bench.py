@@ -71,17 +71,17 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(shape_name):
-    """HBM bytes per launch from the committed counter summary, or None when it
-    is missing or was taken on a different kernel source or shape."""
+def measured_traffic(kname):
+    """HBM bytes per launch of kernel kname from the committed counter summary,
+    or None when it is missing or was taken on a different kernel source."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("source_sha") != kernel_source_sha() or t.get("shape") != shape_name:
+    if t.get("source_sha") != kernel_source_sha():
         return None
-    return t.get("bytes_per_launch")
+    return t.get("kernels", {}).get(kname, {}).get("bytes_per_launch")
 
 
 def cpu_baseline(pr, wl):
@@ -150,28 +150,25 @@ def adjoint_ratio(eed4, torch, args):
             "workload": f"adjoint16: {B} x {H}x{W}, {wl.M} cycles of {wl.n}, checkpoint per cycle"}
 
 
-def probe(eed4, torch, u_init, mask, known, wl):
-    """Let the library pick the fused-step shape (one cycle of eed4_inpaint),
-    launch that step 3 x n times, then copy 64 MiB device to device."""
-    u = u_init.clone()
-    eed4.eed4_inpaint(u, mask, known, eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, 1))
-    torch.cuda.synchronize()
-    shape = eed4.eed4_step_shape(1, wl.H, wl.W, eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, 1))
-    log(f"probe: shape {eed4.SHAPE_NAMES[shape]}")
+def probe(eed4, torch, u_init, mask, wl):
+    """For every fused-step shape (each is its own kernel), launch the step
+    3 x n times; then copy 64 MiB device to device."""
     a, b, c = u_init.clone(), u_init.clone(), u_init.clone()
-    ps = eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, 1, flags=eed4.EED4_FORCE_SHAPE(shape))
     roles = lambda k: (a, a, b) if k == 0 else ((b, a, c) if k == 1 else
                                                  ((b, c, c) if k % 2 else (c, b, b)))
-    for _ in range(3):
-        for k in range(wl.n):
-            cur, prev, out = roles(k)
-            eed4.eed4_fsi_step(cur, prev, out, mask, ps, k)
-    torch.cuda.synchronize()
+    for shape, name in enumerate(eed4.SHAPE_NAMES):
+        ps = eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, 1, flags=eed4.EED4_FORCE_SHAPE(shape))
+        for _ in range(3):
+            for k in range(wl.n):
+                cur, prev, out = roles(k)
+                eed4.eed4_fsi_step(cur, prev, out, mask, ps, k)
+        torch.cuda.synchronize()
+        log(f"probe: {name}")
     src = torch.ones(16 << 20, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
-    log(f"probe done: {3 * wl.n} step launches, one copy of {src.numel() * 4} bytes")
+    log(f"probe done: {3 * wl.n} step launches per shape, one copy of {src.numel() * 4} bytes")
 
 
 def batched_vs_single(eed4, torch, cycles):
@@ -297,7 +294,7 @@ def main():
     wsv = aligned_workspace(torch, eed4.eed4_workspace_size(eed4.EED4_OP_INPAINT, 1, H, W, pt), dev)
 
     if args.probe:
-        probe(eed4, torch, u_init, mask, known, wl)
+        probe(eed4, torch, u_init, mask, wl)
         return
 
     # ---- whole-path timing: warmup cycles, then exactly K timed cycles ----
@@ -362,8 +359,8 @@ def main():
     R = eed4.eed4_radius(wl.sigma)
     per_launch_flops = flops_per_update(R) * H * W
     tflops = per_launch_flops / (kms * 1e-3) / 1e12
-    traffic = measured_traffic(shape_name)
     kname = kernel_name(shape_name, R)
+    traffic = measured_traffic(kname)
     log(f"fused step kernel {kname}: {kms * 1e3:.1f} us/launch, {achieved:.0f} GB/s, "
         f"{tflops:.1f} TFLOP/s")
 
