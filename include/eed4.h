@@ -161,7 +161,12 @@ int eed4_fsi_step(const float *ucur, const float *uprev, float *uout,
 
 /* Adjoint of eed4_inpaint run for exactly M cycles with tol == 0 (the FSI
  * evolution differentiated by hand; the paper gives the forward scheme only).
- * Each cycle is recomputed from its checkpoint, then reversed step by step.
+ * Each cycle is recomputed from its checkpoint, then reversed step by step;
+ * the recompute of cycle m-1 runs on a library-owned stream (one per device,
+ * default priority) while cycle m is reversed on `stream`, ordered by events,
+ * and `stream` waits for all of it: work on `stream` after the call sees
+ * every result, as for any stream-ordered call.  The first call for a problem
+ * size times the reverse-step kernels once (cached per process).
  *  ckpt        [M][B][H][W] cycle-start states as written by eed4_inpaint.
  *  grad_u      [B][H][W] dL/du^{M,0}.
  *  grad_known  [B][H][W] out: dL/df (0 off the mask).

@@ -823,7 +823,8 @@ static BackwardLayout backward_layout(int B, int H, int W, int n, int R)
     const size_t N = (size_t)B * H * W;
     const size_t items = (size_t)max_adjoint_items(R, H, W) * B;
     size_t o = 0;
-    L.U = o; o = align_up(o + sizeof(float) * N * (size_t)(n > 1 ? n - 1 : 1));
+    // two sets of recompute buffers: cycle m-1 is recomputed while cycle m is reversed
+    L.U = o; o = align_up(o + sizeof(float) * N * 2 * (size_t)(n > 1 ? n - 1 : 1));
     L.an = o; o = align_up(o + sizeof(float) * N);
     L.ac = o; o = align_up(o + sizeof(float) * N);
     L.ap = o; o = align_up(o + sizeof(float) * N);
@@ -949,34 +950,73 @@ extern "C" int eed4_backward(const float *ckpt, const uint8_t *mask, const float
     EED4_TRY(launch_fill_double(t.lp, 2 * (size_t)items * B, s), "fill");
     EED4_TRY(hipMemcpyAsync((void *)t.an, grad_u, sizeof(float) * N, hipMemcpyDeviceToDevice, s),
              "seed copy");
-    std::vector<const float *> U(n);
-    float *an = (float *)t.an, *ac = t.ac, *ap = t.ap;
-    for (int m = M - 1; m >= 0; --m) {
-        // recompute u^{m,1..n-1} from the checkpoint
+
+    // The recompute of cycle m-1 (from its checkpoint) does not depend on the
+    // reverse sweep of cycle m: it runs on a second stream into the other
+    // buffer set.  rec[j] marks set j recomputed, done[j] marks the reverse
+    // sweep that read set j finished (a stream wait takes the event's latest
+    // record at the time of the call, so two of each suffice).
+    hipStream_t s1 = recompute_stream();
+    if (!s1) return hip_fail(hipErrorInvalidValue, "recompute stream");
+    hipEvent_t ev[5] = {};
+    for (auto &x : ev) {
+        e = hipEventCreateWithFlags(&x, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            for (auto &y : ev) if (y) (void)hipEventDestroy(y);
+            return hip_fail(e, "event");
+        }
+    }
+    hipEvent_t *rec = ev, *done = ev + 2, start = ev[4];
+    const size_t nU = (size_t)(n > 1 ? n - 1 : 1);
+    float *Uset[2] = {Ubuf, Ubuf + nU * N};
+    std::vector<const float *> Ur[2] = {std::vector<const float *>(n), std::vector<const float *>(n)};
+    auto recompute = [&](int m) -> hipError_t {   // u^{m,1..n-1} from the checkpoint, on s1
+        std::vector<const float *> &U = Ur[m & 1];
         U[0] = ckpt + (size_t)m * N;
         for (int k = 0; k + 1 < n; ++k) {
-            float *out = Ubuf + (size_t)k * N;
+            float *out = Uset[m & 1] + (size_t)k * N;
             StepArgs a = make_args(p->sigma, R, p->tau, p->lambda, k);
-            EED4_TRY(launch_step(R, fshape, U[k], U[k > 0 ? k - 1 : 0], out, nullptr, mask, B, H,
-                                 W, a, nullptr, s),
-                     "recompute step");
+            hipError_t r = launch_step(R, fshape, U[k], U[k > 0 ? k - 1 : 0], out, nullptr, mask,
+                                       B, H, W, a, nullptr, s1);
+            if (r != hipSuccess) return r;
             U[k + 1] = out;
         }
-        EED4_TRY(launch_fill(ac, N, 0.0f, s), "fill");
-        for (int k = n - 1; k >= 0; --k) {
+        return hipEventRecord(rec[m & 1], s1);
+    };
+    float *an = (float *)t.an, *ac = t.ac, *ap = t.ap;
+    int rc2 = EED4_OK;
+#define EED4_TRY2(x, what)                                                  \
+    if (rc2 == EED4_OK && (e = (x)) != hipSuccess) rc2 = hip_fail(e, what)
+    EED4_TRY2(hipEventRecord(start, s), "event record");      // the seed and the checkpoints
+    EED4_TRY2(hipStreamWaitEvent(s1, start, 0), "stream wait");
+    EED4_TRY2(recompute(M - 1), "recompute step");
+    for (int m = M - 1; m >= 0 && rc2 == EED4_OK; --m) {
+        EED4_TRY2(hipStreamWaitEvent(s, rec[m & 1], 0), "stream wait");
+        if (m >= 1) {
+            // set (m-1) & 1 was last read by the reverse sweep of cycle m+1
+            if (m + 1 <= M - 1) EED4_TRY2(hipStreamWaitEvent(s1, done[(m + 1) & 1], 0), "stream wait");
+            EED4_TRY2(recompute(m - 1), "recompute step");
+        }
+        EED4_TRY2(launch_fill(ac, N, 0.0f, s), "fill");
+        const std::vector<const float *> &U = Ur[m & 1];
+        for (int k = n - 1; k >= 0 && rc2 == EED4_OK; --k) {
             t.u = U[k];
             t.an = an;
             t.ac = ac;
             t.ap = ap;
             t.first = k == 0 ? 1 : 0;
-            EED4_TRY(launch_reverse_step(t, p, k, s), "reverse step");
+            EED4_TRY2(launch_reverse_step(t, p, k, s), "reverse step");
             // ubar^k is complete in ac; ap holds the start of ubar^{k-1}
             float *tmp = an;
             an = ac;
             ac = ap;
             ap = tmp;
         }
+        EED4_TRY2(hipEventRecord(done[m & 1], s), "event record");
     }
+#undef EED4_TRY2
+    for (auto &x : ev) (void)hipEventDestroy(x);
+    if (rc2 != EED4_OK) return rc2;
     EED4_TRY(launch_adjoint_final(an, mask, grad_known, grad_init, N, s), "final");
     EED4_TRY(launch_lambda_reduce(t.lp, items, B, acc, s), "lambda reduce");
     EED4_TRY(launch_lambda_store(acc, grad_lambda, B, s), "lambda store");

@@ -63,21 +63,27 @@ StepArgs make_args(float sigma, int R, float tau, float lambda, int k)
     return a;
 }
 
-hipStream_t capture_stream()
+// One library-owned, non-blocking, default-priority stream per device and
+// role (0: graph capture, 1: the backward's recompute).
+static hipStream_t library_stream(int role)
 {
     static std::mutex mu;
-    static std::vector<hipStream_t> streams;
+    static std::vector<hipStream_t> streams[2];
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return nullptr;
     std::lock_guard<std::mutex> lk(mu);
-    if ((int)streams.size() <= dev) streams.resize(dev + 1, nullptr);
-    if (!streams[dev]) {
+    std::vector<hipStream_t> &v = streams[role];
+    if ((int)v.size() <= dev) v.resize(dev + 1, nullptr);
+    if (!v[dev]) {
         hipStream_t s = nullptr;
         if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
-        streams[dev] = s;
+        v[dev] = s;
     }
-    return streams[dev];
+    return v[dev];
 }
+
+hipStream_t capture_stream() { return library_stream(0); }
+hipStream_t recompute_stream() { return library_stream(1); }
 
 // Rotation of the three state buffers over one cycle: S (cycle start and
 // result), X, Y.  Step k reads cur = u^k (with halo) and prev = u^{k-1}

@@ -53,6 +53,7 @@ int tune_single_step(const eed4_params *p, int B, int H, int W, float *S, float 
                      const uint8_t *mask, hipStream_t s, int *shape);
 StepArgs make_args(float sigma, int R, float tau, float lambda, int k);
 hipStream_t capture_stream();
+hipStream_t recompute_stream();
 void cycle_roles(int k, int n, float *S, float *X, float *Y, float **cur, float **prev,
                  float **out);
 int enqueue_cycle(const CycleJob &j, hipStream_t s);
