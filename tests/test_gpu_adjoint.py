@@ -80,6 +80,21 @@ def test_each_reverse_step_kernel_matches_oracle(shape, H, W, sigma, n):
             f"{eed4.SHAPE_NAMES[shape]} {H}x{W} s{sigma}")
 
 
+@pytest.mark.parametrize("shape", [0, 3, 6])
+@pytest.mark.parametrize("H,W", [(1, 1), (2, 3), (1, 40), (37, 1)])
+def test_reverse_step_degenerate_sizes(shape, H, W):
+    # one pixel, single rows and columns: every neighbour comes from the
+    # mirror (repeated reflection), in both the recompute and the reverse step
+    announce(f"reverse step {eed4.SHAPE_NAMES[shape]} degenerate {H}x{W}")
+    b = {k: np.stack([make_problem(H, W, 2, True, 0.01, 0.25, 40 + i + 3 * H + W)[k]
+                      for i in range(2)]) for k in ("image", "mask", "known", "u_init")}
+    gu = np.random.default_rng(7 + H * W).normal(size=b["u_init"].shape) * 1e-2
+    _, ck, gk, gi, gl = gpu_forward_backward(b, 0.05, 1.0, 0.05, 4, 2, gu,
+                                             flags=eed4.EED4_FORCE_SHAPE(shape))
+    compare(b, ck, gk, gi, gl, 0.05, 1.0, 0.05, 4, gu,
+            f"{eed4.SHAPE_NAMES[shape]} {H}x{W}")
+
+
 def test_adjoint_tile_kernel_recompute():
     announce("adjoint with the tile step kernel for the recompute")
     b = {k: v[None] for k, v in make_problem(48, 60, 4, True, 0.01, 0.06, 31).items()
