@@ -251,7 +251,8 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100, help="timed FSI cycles")
-    ap.add_argument("--warmup", type=int, default=5, help="untimed FSI cycles")
+    ap.add_argument("--warmup", type=int, default=30,
+                    help="untimed FSI cycles (the GPU clock needs some tens of ms of work to settle)")
     ap.add_argument("--kernel-reps", type=int, default=20,
                     help="cycles of back-to-back eed4_fsi_step launches for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -338,10 +339,10 @@ def main():
             return b, a, c
         return (b, c, c) if k % 2 else (c, b, b)
 
-    # three windows of kernel_reps cycles each; the median window is reported
+    # five windows of kernel_reps cycles each; the median window is reported
     # (the first launches after a pause run at a lower clock)
     windows = []
-    for _ in range(3):
+    for _ in range(5):
         launches = 0
         e2.record(stream)
         for _ in range(args.kernel_reps):
@@ -352,7 +353,7 @@ def main():
         e3.record(stream)
         torch.cuda.synchronize()
         windows.append(e2.elapsed_time(e3) / launches)
-    kms = sorted(windows)[1]
+    kms = sorted(windows)[2]
     log("fused step windows: " + ", ".join(f"{w * 1e3:.1f}" for w in windows) + " us/launch")
     per_launch_bytes = BYTES_PER_UPDATE * H * W
     achieved = per_launch_bytes / (kms * 1e-3) / 1e9
