@@ -203,6 +203,23 @@ def test_every_step_shape_and_the_autotuned_default(H, W, B):
     assert np.array_equal(outs[None], outs[0]) or np.array_equal(outs[None], outs[3])
 
 
+@pytest.mark.parametrize("shape", [2, 3, 5, 7])
+@pytest.mark.parametrize("H,W", [(1, 70000), (50000, 3)])
+def test_long_thin_images_one_cycle(shape, H, W):
+    # the most strips (or segments) per image along one axis, the fewest along
+    # the other: strip and row offsets at their largest for the image size
+    announce(f"long thin {H}x{W}, shape {eed4.SHAPE_NAMES[shape]}")
+    pr = make_problem(H, W, 6, True, 0.01, 0.05, 321 + H)
+    u0 = np.where(pr["mask"] != 0, pr["known"], pr["u_init"]).astype(np.float32)
+    got, sums = gpu_cycle(u0[None], pr["mask"][None], pr["known"][None], 0.04, 1.5, 0.05, 6,
+                          flags=eed4.EED4_FORCE_SHAPE(shape))
+    ref, rh = oracle_cycle(u0[None], pr["mask"][None], pr["known"][None], 0.04, 1.5, 0.05, 6)
+    e = rel_l2(got[0], ref[0])
+    print(f"{H}x{W} {eed4.SHAPE_NAMES[shape]}: rel L2 {e:.3e}")
+    assert e <= REL_L2_PER_CYCLE
+    assert np.allclose(np.sqrt(sums[0, 1]), rh[0, 0, 1], rtol=1e-6)
+
+
 def test_large4096_first_cycle_parity():
     wl = WORKLOADS["large4096"]
     announce("large4096 first cycle (bench launch configuration) vs oracle")
