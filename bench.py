@@ -92,9 +92,43 @@ def cpu_baseline(pr, wl):
     dt = time.perf_counter() - t0
     upd = pr["u_init"].size * n
     return {"value": upd / dt / 1e6, "unit": "Mpixel-updates/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu": cpu_model(),
             "sample": f"one FSI cycle ({n} steps) of the full {wl.H}x{wl.W} workload image, "
                       f"FP64, {dt:.1f} s"}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def copy_bandwidth(torch):
+    """Achieved GB/s (read + write bytes) of a plain device-to-device copy:
+    1 GiB (beyond the 256 MB Infinity Cache) and 64 MiB (one image plane)."""
+    out = {}
+    for label, nbytes in (("copy_1GiB", 1 << 30), ("copy_64MiB", 64 << 20)):
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        reps = 20
+        e0.record()
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        out[label] = round(2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+        del a, b
+    out["unit"] = "GB/s"
+    return out
 
 
 def aligned_workspace(torch, nbytes, dev):
@@ -390,7 +424,8 @@ def main():
                      "hbm": {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": round(achieved / HBM_PEAK_GBS, 4),
                              "algorithmic_bytes_per_launch": per_launch_bytes},
-                     "kernel_source_sha": kernel_source_sha()},
+                     "kernel_source_sha": kernel_source_sha(),
+                     "copy_context": copy_bandwidth(torch)},
     }
     if not args.no_adjoint:
         log("adjoint / forward timing (16 x 256x256)")
