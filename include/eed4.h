@@ -73,12 +73,14 @@ extern "C" {
 #define EED4_TILE_KERNEL     0x8
 
 /* Use kernel shape s for the fused step instead of the automatic choice
- * (the autotuner in eed4_inpaint_batched, a work-size rule elsewhere):
+ * (the autotuners of eed4_inpaint and eed4_inpaint_batched; eed4_fsi_cycle,
+ * eed4_fsi_step and eed4_backward use the choice eed4_inpaint made for the
+ * same problem size, else a work-size rule):
  * 0: 64x32 workgroup tiles, 1: 64x16 tiles, 2: 32x32 tiles, 3: wave strips of
  * 60 columns x >= 64 rows, 4: strips of >= 136 rows, 5: strips of >= 28 rows,
  * 6: strips of >= 8 rows, 7: strips of 124 columns (two per lane) x >= 64 rows,
  * 8: 124-column strips of >= 28 rows.
- * All strip heights give bitwise the same results; so do all tile shapes. */
+ * All strip shapes give bitwise the same results; so do all tile shapes. */
 #define EED4_FORCE_SHAPE(s)  ((((s) + 1) & 0xff) << 8)
 
 /* ---- workspace sizing (eed4_workspace_size op) ---- */
@@ -182,9 +184,9 @@ int eed4_backward(const float *ckpt, const uint8_t *mask, const float *known,
 size_t eed4_batched_workspace_size(const eed4_image *imgs, int B,
                                    const eed4_params *p);
 
-/* Inpaint B images of uneven sizes with one persistent launch per inner step
- * over a tile work-queue spanning all images; the cycle is replayed as a
- * captured hipGraph.  sigma, tau, n, M, tol and flags come from p; lambda
+/* Inpaint B images of uneven sizes with one launch per inner step over a
+ * work queue of tiles or strip segments spanning all images; the cycle is
+ * replayed as a captured hipGraph.  sigma, tau, n, M, tol and flags come from p; lambda
  * from each image.  imgs is a HOST array.  stats: NULL or HOST [B]; an image
  * whose residual falls below tol stops and leaves the queue (per-image stop).
  * Results equal eed4_inpaint on each image alone. */

@@ -1,8 +1,8 @@
-// Batched inpainting of images of uneven sizes: one persistent launch per
-// inner FSI step over a work queue spanning every image, the cycle captured
-// once as a hipGraph, per-image stop, and an autotuner that picks the kernel
-// shape (workgroup tiles or wave strips of two heights) by timing one step on
-// the actual batch.
+// Batched inpainting of images of uneven sizes: one launch per inner FSI step
+// over a work queue spanning every image, the cycle captured once as a
+// hipGraph, per-image stop, and an autotuner that picks the kernel shape
+// (workgroup tiles, or wave strips of four heights and two widths) by timing
+// one step on the actual batch.
 //
 // The queue holds one entry per work item (a tile of a workgroup, or a strip
 // segment of a wave) of every image still iterating.  A launch has one wave or
