@@ -169,6 +169,42 @@ def test_stop_rule_and_steady_state_512():
     assert e <= RMSE_STEADY
 
 
+def test_abs_tol_stop_rule_matches_oracle():
+    # plain residual ||u^{m,n} - u^{m,0}||_2 < tol (EED4_ABS_TOL), as Sec. 3.3 states it
+    announce("absolute stop rule, 96x80, tol 1e-2")
+    pr = make_problem(96, 80, 8, True, 0.01, 0.05, 808)
+    lam, sigma, tau, n, M, tol = 0.04, 1.5, 0.05, 10, 150, 1e-2
+    u = to_dev(pr["u_init"])
+    st, hist = eed4.eed4_inpaint(u, to_dev(pr["mask"]), to_dev(pr["known"]),
+                                 eed4.params(lam, sigma, tau, n, M, tol=tol,
+                                             flags=eed4.EED4_ABS_TOL), history=True)
+    got = u.cpu().numpy()
+    res = hist[:, 0, 0]
+    _, ocyc, _ = oracle.inpaint(pr["u_init"], pr["mask"], pr["known"], lam, sigma, tau, n, M,
+                                tol=tol, abs_tol=True)
+    print(f"absolute stop: GPU {st.cycles} cycles (residual {st.residual:.4e}), oracle {ocyc}")
+    assert st.cycles < M and res[-1] < tol and np.all(res[:-1] >= tol)
+    assert st.residual == pytest.approx(res[-1], rel=1e-6)
+    assert abs(st.cycles - ocyc) <= 1     # FP32 residual against FP64, 3 % apart per cycle
+    ref, _, _ = oracle.inpaint(pr["u_init"], pr["mask"], pr["known"], lam, sigma, tau, n,
+                               st.cycles)
+    assert rmse(got, ref) <= RMSE_STEADY
+
+
+@pytest.mark.parametrize("tol", [0.0, 1e-4])
+def test_divergence_is_reported(tol):
+    # tau = 0.4 is far beyond the bound 1/16 (allowed by flag): the state
+    # overflows FP32 within about 45 steps, and the call must say so
+    announce(f"divergence at tau 0.4, tol {tol}")
+    pr = make_problem(64, 64, 5, False, 0.01, 0.05, 77)
+    u = to_dev(pr["u_init"])
+    with pytest.raises(eed4.EED4Error) as err:
+        eed4.eed4_inpaint(u, to_dev(pr["mask"]), to_dev(pr["known"]),
+                          eed4.params(0.05, 1.0, 0.4, 10, 8, tol=tol,
+                                      flags=eed4.EED4_ALLOW_LARGE_TAU))
+    assert err.value.code == eed4._lib.EED4_EDIVERGED
+
+
 def test_strip_and_tile_kernels_agree():
     announce("strip vs tile kernel, 300x260, 3 cycles")
     pr = make_problem(300, 260, 12, True, 0.01, 0.04, 555)
