@@ -125,14 +125,19 @@ int enqueue_cycle(const CycleJob &j, hipStream_t s)
     return EED4_OK;
 }
 
-int capture_cycle(const CycleJob &j, hipGraphExec_t *exec)
+// Records what `enqueue` puts on the library's capture stream into an
+// executable graph.  That stream is shared by all host threads of the process,
+// so captures are serialised; a capture only records launches.
+int capture_graph(const std::function<int(hipStream_t)> &enqueue, hipGraphExec_t *exec)
 {
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lk(mu);
     *exec = nullptr;
     hipStream_t cs = capture_stream();
     if (!cs) return hip_fail(hipErrorInvalidValue, "capture stream");
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "begin capture");
-    int rc = enqueue_cycle(j, cs);
+    int rc = enqueue(cs);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(cs, &g);
     if (rc != EED4_OK) {
@@ -144,6 +149,11 @@ int capture_cycle(const CycleJob &j, hipGraphExec_t *exec)
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(e, "graph instantiate");
     return EED4_OK;
+}
+
+int capture_cycle(const CycleJob &j, hipGraphExec_t *exec)
+{
+    return capture_graph([&](hipStream_t cs) { return enqueue_cycle(j, cs); }, exec);
 }
 
 struct InpaintLayout {

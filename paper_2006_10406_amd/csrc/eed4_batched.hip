@@ -538,21 +538,8 @@ extern "C" int eed4_inpaint_batched(const eed4_image *imgs, int B, const eed4_pa
 
     hipGraphExec_t exec = nullptr;
     if (!(p->flags & EED4_NO_GRAPH)) {
-        hipStream_t cs = capture_stream();
-        if (!cs) return hip_fail(hipErrorInvalidValue, "capture stream");
-        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) return hip_fail(e, "begin capture");
-        rc = enqueue_bcycle(r, cs);
-        hipGraph_t g = nullptr;
-        e = hipStreamEndCapture(cs, &g);
-        if (rc != EED4_OK) {
-            if (g) (void)hipGraphDestroy(g);
-            return rc;
-        }
-        if (e != hipSuccess) return hip_fail(e, "end capture");
-        e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+        rc = capture_graph([&](hipStream_t cs) { return enqueue_bcycle(r, cs); }, &exec);
+        if (rc != EED4_OK) return rc;
     }
 
     const int M = p->max_cycles;

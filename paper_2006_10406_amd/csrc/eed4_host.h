@@ -4,6 +4,7 @@
 #include "eed4.h"
 #include "eed4_internal.h"
 
+#include <functional>
 #include <string>
 
 namespace eed4 {
@@ -57,6 +58,7 @@ hipStream_t recompute_stream();
 void cycle_roles(int k, int n, float *S, float *X, float *Y, float **cur, float **prev,
                  float **out);
 int enqueue_cycle(const CycleJob &j, hipStream_t s);
+int capture_graph(const std::function<int(hipStream_t)> &enqueue, hipGraphExec_t *exec);
 int capture_cycle(const CycleJob &j, hipGraphExec_t *exec);
 size_t backward_workspace(int B, int H, int W, const eed4_params *p);
 

@@ -205,6 +205,43 @@ def test_divergence_is_reported(tol):
     assert err.value.code == eed4._lib.EED4_EDIVERGED
 
 
+def test_concurrent_host_threads():
+    # two host threads in eed4_inpaint at once (ctypes drops the GIL), each on
+    # its own stream: graph capture is shared per process and must not clash
+    import threading
+    announce("two host threads calling eed4_inpaint concurrently")
+    probs = [make_problem(160, 200, 6, True, 0.01, 0.05, 900 + i) for i in range(2)]
+    p = eed4.params(0.04, 1.5, 0.05, 10, 6)
+
+    def run(pr, stream=None):
+        u = to_dev(pr["u_init"])
+        eed4.eed4_inpaint(u, to_dev(pr["mask"]), to_dev(pr["known"]), p, stream=stream)
+        return u
+
+    ref = [run(pr).cpu().numpy() for pr in probs]
+    torch.cuda.synchronize()
+    for _ in range(3):
+        streams = [torch.cuda.Stream() for _ in probs]
+        outs, errs = [None, None], []
+
+        def work(i):
+            try:
+                with torch.cuda.stream(streams[i]):
+                    outs[i] = run(probs[i], streams[i])
+                streams[i].synchronize()
+            except Exception as exc:        # reported below, on the main thread
+                errs.append(exc)
+
+        ts = [threading.Thread(target=work, args=(i,)) for i in range(2)]
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
+        assert not errs, errs
+        for i in range(2):
+            assert np.array_equal(outs[i].cpu().numpy(), ref[i])
+
+
 def test_strip_and_tile_kernels_agree():
     announce("strip vs tile kernel, 300x260, 3 cycles")
     pr = make_problem(300, 260, 12, True, 0.01, 0.04, 555)
