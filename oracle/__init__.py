@@ -38,27 +38,30 @@ def _lib():
         L.oracle_gauss.argtypes = [ctypes.c_double, ctypes.c_int, _dp]
         L.oracle_charbonnier.restype = ctypes.c_double
         L.oracle_charbonnier.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.oracle_diffusivity.restype = ctypes.c_double
+        L.oracle_diffusivity.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int]
         L.oracle_alpha.restype = ctypes.c_double
         L.oracle_alpha.argtypes = [ctypes.c_int]
-        L.oracle_tensor.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
+        ci = ctypes.c_int
+        L.oracle_tensor.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, ci, ci, _dp]
         L.oracle_e_grad.argtypes = [ctypes.c_double, ctypes.c_double, _dp, _dp,
-                                    ctypes.c_double, _dp, _dp, _dp]
+                                    ctypes.c_double, ci, ci, _dp, _dp, _dp]
         L.oracle_apply_P.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_int,
-                                     ctypes.c_double, ctypes.c_double, _dp]
+                                     ctypes.c_double, ctypes.c_double, ci, ci, _dp]
         L.oracle_hessian.argtypes = [_dp, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]
         L.oracle_gradient.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp]
         L.oracle_step.argtypes = [_dp, _dp, _u8p, _dp, ctypes.c_int, ctypes.c_int,
-                                  ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_double, ci, ci, ctypes.c_double,
                                   ctypes.c_int, _dp]
         L.oracle_inpaint.restype = ctypes.c_int
         L.oracle_inpaint.argtypes = [_dp, _u8p, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_double, ci, ci, ctypes.c_double,
                                      ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                      _dp, _dp]
         L.oracle_jtv.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
-                                 ctypes.c_double, _dp, _dp]
+                                 ctypes.c_double, ci, ci, _dp, _dp]
         L.oracle_backward.argtypes = [_dp, _u8p, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                      ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, ci, ci, ctypes.c_double,
                                       ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp]
         _LIB = L
     return _LIB
@@ -97,36 +100,51 @@ def charbonnier(s2: float, lam: float) -> float:
     return _lib().oracle_charbonnier(float(s2), float(lam))
 
 
+#: Diffusivities of Table 7 by index (``diff`` argument); Geman-Reynolds is
+#: scaled to g(0) = 1.
+DIFFUSIVITIES = ("charbonnier", "perona_malik", "perona_malik_exp", "geman_reynolds")
+#: Choices of mu_3 from mu_1 = g and mu_2 = 1 (Sec. 3.1, Table 1) by index
+#: (``mu3`` argument): geometric mean (FOEED), arithmetic mean, maximum.
+MU3_RULES = ("geometric", "arithmetic", "max")
+
+
+def diffusivity(s2: float, lam: float, diff: int = 0) -> float:
+    """g(s^2) of diffusivity ``diff`` (index into DIFFUSIVITIES), Table 7."""
+    return _lib().oracle_diffusivity(float(s2), float(lam), int(diff))
+
+
 def alpha(k: int) -> float:
     """FSI extrapolation weight alpha_k = (4k+2)/(2k+3) (Sec. 3.3)."""
     return _lib().oracle_alpha(int(k))
 
 
-def tensor(gx: float, gy: float, lam: float) -> np.ndarray:
+def tensor(gx: float, gy: float, lam: float, diff: int = 0, mu3: int = 0) -> np.ndarray:
     """d_ijkl as a 4x4 array indexed [(i,j), (k,l)] in the order xx, xy, yx, yy
     (eqs. faod_diffTensor, foad_diffTensor_entries)."""
     d = np.zeros(16)
-    _lib().oracle_tensor(float(gx), float(gy), float(lam), d.ctypes.data_as(_dp))
+    _lib().oracle_tensor(float(gx), float(gy), float(lam), int(diff), int(mu3),
+                         d.ctypes.data_as(_dp))
     return d.reshape(4, 4)
 
 
-def e_grad(gx, gy, A, Hm, lam):
+def e_grad(gx, gy, A, Hm, lam, diff=0, mu3=0):
     """e = A : D(G) : H, de/dG and de/dlambda for 2x2 A, H (adjoint helper)."""
     A, pa = _d(np.asarray(A).reshape(4))
     Hm, ph = _d(np.asarray(Hm).reshape(4))
     e = np.zeros(1); q = np.zeros(2); dl = np.zeros(1)
-    _lib().oracle_e_grad(float(gx), float(gy), pa, ph, float(lam),
+    _lib().oracle_e_grad(float(gx), float(gy), pa, ph, float(lam), int(diff), int(mu3),
                          e.ctypes.data_as(_dp), q.ctypes.data_as(_dp), dl.ctypes.data_as(_dp))
     return float(e[0]), q, float(dl[0])
 
 
-def apply_P(ut, x, lam, sigma):
+def apply_P(ut, x, lam, sigma, diff=0, mu3=0):
     """P(ut) x: tensor from the presmoothed gradient of ut, applied to x."""
     ut, pu = _d(ut)
     x, px = _d(x)
     H, W = ut.shape
     out = np.zeros((H, W))
-    _lib().oracle_apply_P(pu, px, H, W, float(lam), float(sigma), out.ctypes.data_as(_dp))
+    _lib().oracle_apply_P(pu, px, H, W, float(lam), float(sigma), int(diff), int(mu3),
+                          out.ctypes.data_as(_dp))
     return out
 
 
@@ -149,7 +167,7 @@ def gradient(u, sigma):
     return gx, gy
 
 
-def step(u, uprev, mask, f, lam, sigma, tau, k):
+def step(u, uprev, mask, f, lam, sigma, tau, k, diff=0, mu3=0):
     """One FSI inner step with Dirichlet hold (Sec. 3.3, eq. genModel)."""
     u, pu = _d(u)
     uprev, pp = _d(uprev)
@@ -159,13 +177,13 @@ def step(u, uprev, mask, f, lam, sigma, tau, k):
     mask, pm = _m(mask)
     f, pf = _d(np.zeros((H, W)) if f is None else f)
     out = np.zeros((H, W))
-    _lib().oracle_step(pu, pp, pm, pf, H, W, float(lam), float(sigma), float(tau), int(k),
-                       out.ctypes.data_as(_dp))
+    _lib().oracle_step(pu, pp, pm, pf, H, W, float(lam), float(sigma), int(diff), int(mu3),
+                       float(tau), int(k), out.ctypes.data_as(_dp))
     return out
 
 
 def inpaint(u_init, mask, known, lam, sigma, tau, n, M, tol=0.0, abs_tol=False,
-            checkpoints=False):
+            checkpoints=False, diff=0, mu3=0):
     """FOEED inpainting of one image [H,W] or an equal-size batch [B,H,W].
 
     Returns (u, cycles, hist[, ckpt]) with hist[m, b] = (||u^{m,n}-u^{m,0}||,
@@ -180,7 +198,8 @@ def inpaint(u_init, mask, known, lam, sigma, tau, n, M, tol=0.0, abs_tol=False,
     hist = np.zeros((M, B, 2))
     ck = np.zeros((M, B, H, W)) if checkpoints else None
     cyc = _lib().oracle_inpaint(u.ctypes.data_as(_dp), pm, pf, B, H, W, float(lam), float(sigma),
-                                float(tau), int(n), int(M), float(tol), int(bool(abs_tol)),
+                                int(diff), int(mu3), float(tau), int(n), int(M), float(tol),
+                                int(bool(abs_tol)),
                                 ck.ctypes.data_as(_dp) if ck is not None else None,
                                 hist.ctypes.data_as(_dp))
     hist = hist[:cyc]
@@ -194,18 +213,18 @@ def inpaint(u_init, mask, known, lam, sigma, tau, n, M, tol=0.0, abs_tol=False,
     return u, cyc, hist
 
 
-def jtv(u, w, lam, sigma):
+def jtv(u, w, lam, sigma, diff=0, mu3=0):
     """(J_F(u)^T w, <dF/dlambda, w>) for F(u) = P(u) u."""
     u, pu = _d(u)
     w, pw = _d(w)
     H, W = u.shape
     out = np.zeros((H, W)); dl = np.zeros(1)
-    _lib().oracle_jtv(pu, pw, H, W, float(lam), float(sigma), out.ctypes.data_as(_dp),
-                      dl.ctypes.data_as(_dp))
+    _lib().oracle_jtv(pu, pw, H, W, float(lam), float(sigma), int(diff), int(mu3),
+                      out.ctypes.data_as(_dp), dl.ctypes.data_as(_dp))
     return out, float(dl[0])
 
 
-def backward(ckpt, mask, known, lam, sigma, tau, n, grad_u):
+def backward(ckpt, mask, known, lam, sigma, tau, n, grad_u, diff=0, mu3=0):
     """Adjoint of ``inpaint`` run for exactly len(ckpt) cycles.
 
     ckpt: [M,H,W] or [M,B,H,W] cycle-start states; grad_u: dL/du^{M,0}.
@@ -220,7 +239,8 @@ def backward(ckpt, mask, known, lam, sigma, tau, n, grad_u):
     f, pf = _d(np.asarray(known).reshape(B, H, W))
     gu, pg = _d(np.asarray(grad_u).reshape(B, H, W))
     gf = np.zeros((B, H, W)); gi = np.zeros((B, H, W)); gl = np.zeros(B)
-    _lib().oracle_backward(pc, pm, pf, B, H, W, float(lam), float(sigma), float(tau), int(n),
+    _lib().oracle_backward(pc, pm, pf, B, H, W, float(lam), float(sigma), int(diff), int(mu3),
+                           float(tau), int(n),
                            int(M), pg, gf.ctypes.data_as(_dp), gi.ctypes.data_as(_dp),
                            gl.ctypes.data_as(_dp))
     if single:

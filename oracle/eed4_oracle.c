@@ -24,7 +24,9 @@
  *  - the gradient of u_sigma uses central differences;
  *  - the diffusion tensor is recomputed at every inner FSI step (Sec. 3.3
  *    writes P(u^{m,k}));
- *  - the cycle residual may be taken relative to ||u^{m,n}||_2.
+ *  - the cycle residual may be taken relative to ||u^{m,n}||_2;
+ *  - Table 7's Geman-Reynolds diffusivity is scaled to g(0) = 1 (see
+ *    diffusivity_x); its Aubert entry, which vanishes at s = 0, is left out.
  * Adjoint: derived here from the forward recursion (Sec. 3.3) by the chain
  * rule; it is not in the paper.
  */
@@ -85,6 +87,51 @@ double oracle_charbonnier(double s2, double lam)
     return 1.0 / sqrt(1.0 + s2 / (lam * lam));
 }
 
+/* The diffusivities compared in Table 7, as functions of x = (s/lambda)^2,
+ * and their derivatives dg/dx:
+ *   0 Charbonnier              (1 + x)^(-1/2)            (eq. CharDiff)
+ *   1 Perona-Malik             (1 + x)^(-1)
+ *   2 Perona-Malik exponential exp(-x)
+ *   3 Geman-Reynolds           (1 + x)^(-2)
+ * Table 7 prints the Geman-Reynolds function as 2 lambda^2 / (s^2 +
+ * lambda^2)^2, which is (2 / lambda^2) (1 + x)^(-2); it is used here scaled
+ * to g(0) = 1 like the other three, so that every eigenvalue of the tensor
+ * stays in [0, 1] and the step bound tau <= 1/16 holds for all of them.
+ * (The Aubert entry of the table vanishes at s = 0 and is left out.) */
+static double diffusivity_x(double x, int diff, double *dgdx)
+{
+    double g;
+    switch (diff) {
+    case 1: g = 1.0 / (1.0 + x); *dgdx = -g * g; break;
+    case 2: g = exp(-x); *dgdx = -g; break;
+    case 3: g = 1.0 / ((1.0 + x) * (1.0 + x)); *dgdx = -2.0 * g / (1.0 + x); break;
+    default: g = 1.0 / sqrt(1.0 + x); *dgdx = -0.5 * g * g * g; break;
+    }
+    return g;
+}
+
+double oracle_diffusivity(double s2, double lam, int diff)
+{
+    double d;
+    return diffusivity_x(s2 / (lam * lam), diff, &d);
+}
+
+/* mu_3 from mu_1 = g and mu_2 = 1 (Sec. 3.1, Table 1):
+ *   0 geometric mean sqrt(mu_1 mu_2)  (the paper's choice for FOEED)
+ *   1 arithmetic mean (mu_1 + mu_2)/2
+ *   2 maximum of mu_1 and mu_2 (= 1)
+ * and d mu_3 / d g. */
+static double mu3_of(double g, int rule, double *dmdg)
+{
+    switch (rule) {
+    case 1: *dmdg = 0.5; return 0.5 * (g + 1.0);
+    case 2: *dmdg = 0.0; return g > 1.0 ? g : 1.0;
+    default:   /* g = 0 only where g underflows; there d sqrt(g)/ds -> 0 */
+        *dmdg = g > 0.0 ? 0.5 / sqrt(g) : 0.0;
+        return sqrt(g);
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* the fourth-order diffusion tensor (Sec. 3.1)                              */
 /* ------------------------------------------------------------------------ */
@@ -140,22 +187,31 @@ static void eigentensors(const double v1[2], const double v2[2],
     }
 }
 
-/* Eigenvalues mu_1..mu_4 = g, 1, sqrt(g), 0 (eq. foad_diffTensor_entries,
- * geometric-mean choice of mu_3). */
-static void eigenvalues(double s2, double lam, double mu[4])
+/* Eigenvalues mu_1..mu_4 = g, 1, mu_3(g), 0 (eq. foad_diffTensor_entries)
+ * for diffusivity diff and mu_3 rule mu3 (diff = mu3 = 0 is the paper's
+ * FOEED: Charbonnier, geometric mean), with their derivatives with respect
+ * to s = |grad u_sigma| and to lambda (used by the adjoint). */
+static void eigenvalues(double s2, double lam, int diff, int mu3, double mu[4],
+                        double dmu_ds[4], double dmu_dl[4])
 {
-    double g = oracle_charbonnier(s2, lam);
-    mu[0] = g; mu[1] = 1.0; mu[2] = sqrt(g); mu[3] = 0.0;
+    double l2 = lam * lam, x = s2 / l2, dgdx, dmdg;
+    double g = diffusivity_x(x, diff, &dgdx);
+    double m3 = mu3_of(g, mu3, &dmdg);
+    /* dx/ds = 2 s / lambda^2, dx/dlambda = -2 s^2 / lambda^3 */
+    double gs = dgdx * 2.0 * sqrt(s2) / l2, gl = dgdx * (-2.0 * s2 / (l2 * lam));
+    mu[0] = g; mu[1] = 1.0; mu[2] = m3; mu[3] = 0.0;
+    dmu_ds[0] = gs; dmu_ds[1] = 0.0; dmu_ds[2] = dmdg * gs; dmu_ds[3] = 0.0;
+    dmu_dl[0] = gl; dmu_dl[1] = 0.0; dmu_dl[2] = dmdg * gl; dmu_dl[3] = 0.0;
 }
 
 /* Full 16-coefficient tensor d_ijkl = sum_n mu_n (E_n)_ij (E_n)_kl
  * (eq. faod_diffTensor); d[(2i+j)*4 + (2k+l)]. */
-void oracle_tensor(double gx, double gy, double lam, double d[16])
+void oracle_tensor(double gx, double gy, double lam, int diff, int mu3, double d[16])
 {
-    double v1[2], v2[2], E[4][4], dE[4][4], mu[4];
+    double v1[2], v2[2], E[4][4], dE[4][4], mu[4], ds[4], dl[4];
     directions(gx, gy, v1, v2);
     eigentensors(v1, v2, E, dE);
-    eigenvalues(gx * gx + gy * gy, lam, mu);
+    eigenvalues(gx * gx + gy * gy, lam, diff, mu3, mu, ds, dl);
     for (int a = 0; a < 4; ++a)
         for (int b = 0; b < 4; ++b) {
             double s = 0.0;
@@ -179,17 +235,13 @@ static void contract(const double d[16], const double Hm[4], double T[4])
  * by the adjoint.  G is written in polar form s (cos t, sin t); the mu_n
  * depend on s, the eigentensors on t. */
 void oracle_e_grad(double gx, double gy, const double A[4], const double Hm[4],
-                   double lam, double *e, double q[2], double *dedlam)
+                   double lam, int diff, int mu3, double *e, double q[2], double *dedlam)
 {
-    double v1[2], v2[2], E[4][4], dE[4][4], mu[4];
+    double v1[2], v2[2], E[4][4], dE[4][4], mu[4], dmu_ds[4], dmu_dl[4];
     double s2 = gx * gx + gy * gy, s = sqrt(s2);
     directions(gx, gy, v1, v2);
     eigentensors(v1, v2, E, dE);
-    eigenvalues(s2, lam, mu);
-    double g = mu[0], l2 = lam * lam, l3 = l2 * lam;
-    /* d mu / d s and d mu / d lambda for mu1 = g, mu3 = sqrt(g) */
-    double dmu_ds[4] = { -g * g * g * s / l2, 0.0, -0.5 * pow(g, 2.5) * s / l2, 0.0 };
-    double dmu_dl[4] = { g * g * g * s2 / l3, 0.0, 0.5 * pow(g, 2.5) * s2 / l3, 0.0 };
+    eigenvalues(s2, lam, diff, mu3, mu, dmu_ds, dmu_dl);
     double ee = 0.0, de_ds = 0.0, de_dt = 0.0, de_dl = 0.0;
     for (int n = 0; n < 4; ++n) {
         double aE = ddot2(A, E[n]), hE = ddot2(E[n], Hm);
@@ -225,7 +277,7 @@ static void extend(const double *a, int H, int W, int h, double *e)
  * of ut; the Hessian, the contraction and the outer divergence act on x
  * (eq. genModel; P(u)u is the right-hand side with the sign flipped). */
 void oracle_apply_P(const double *ut, const double *x, int H, int W,
-                    double lam, double sigma, double *out)
+                    double lam, double sigma, int diff, int mu3, double *out)
 {
     int R = oracle_radius(sigma), h = R + 2;
     int He = H + 2 * h, We = W + 2 * h;
@@ -273,7 +325,7 @@ void oracle_apply_P(const double *ut, const double *x, int H, int W,
 #undef V
 #undef X
             double d[16], Hm[4] = { hxx, hxy, hxy, hyy }, Tm[4];
-            oracle_tensor(gx, gy, lam, d);
+            oracle_tensor(gx, gy, lam, diff, mu3, d);
             contract(d, Hm, Tm);
             for (int c = 0; c < 4; ++c) T[((size_t)c * Hp + py) * Wp + px] = Tm[c];
         }
@@ -353,12 +405,12 @@ double oracle_alpha(int k)
  * followed by the Dirichlet condition u = f on the known set K. */
 void oracle_step(const double *u, const double *uprev, const uint8_t *mask,
                  const double *f, int H, int W, double lam, double sigma,
-                 double tau, int k, double *out)
+                 int diff, int mu3, double tau, int k, double *out)
 {
     size_t N = (size_t)H * W;
     double *Pu = malloc(sizeof(double) * N);
     double a = oracle_alpha(k);
-    oracle_apply_P(u, u, H, W, lam, sigma, Pu);
+    oracle_apply_P(u, u, H, W, lam, sigma, diff, mu3, Pu);
     for (size_t i = 0; i < N; ++i) {
         double v = a * (u[i] - tau * Pu[i]) + (1.0 - a) * uprev[i];
         out[i] = (mask && mask[i]) ? f[i] : v;
@@ -375,8 +427,8 @@ void oracle_step(const double *u, const double *uprev, const uint8_t *mask,
  * otherwise after M cycles.  ckpt (may be NULL) receives u^{m,0} per cycle,
  * [M][B][H][W].  Returns the number of cycles run. */
 int oracle_inpaint(double *u, const uint8_t *mask, const double *f,
-                   int B, int H, int W, double lam, double sigma, double tau,
-                   int n, int M, double tol, int abs_tol,
+                   int B, int H, int W, double lam, double sigma, int diff, int mu3,
+                   double tau, int n, int M, double tol, int abs_tol,
                    double *ckpt, double *hist)
 {
     size_t N = (size_t)H * W;
@@ -397,7 +449,8 @@ int oracle_inpaint(double *u, const uint8_t *mask, const double *f,
             memcpy(prev, ub, sizeof(double) * N);
             memcpy(cur, ub, sizeof(double) * N);
             for (int k = 0; k < n; ++k) {
-                oracle_step(cur, prev, mask + b * N, f + b * N, H, W, lam, sigma, tau, k, nxt);
+                oracle_step(cur, prev, mask + b * N, f + b * N, H, W, lam, sigma, diff, mu3,
+                            tau, k, nxt);
                 double *t = prev; prev = cur; cur = nxt; nxt = t;
             }
             memcpy(ub, cur, sizeof(double) * N);
@@ -489,7 +542,7 @@ static void hess_scatter(const double *T, int H, int W, double *out)
  * <w, F(u)> = sum_p (B w)_p : D(G_p) : (B u)_p with G = grad K_sigma u, the
  * gradient with respect to u is B^T (D : B w) + C^T q, q_p = de_p/dG_p. */
 void oracle_jtv(const double *u, const double *wv, int H, int W, double lam,
-                double sigma, double *out, double *dlam)
+                double sigma, int diff, int mu3, double *out, double *dlam)
 {
     int R = oracle_radius(sigma);
     size_t N = (size_t)H * W;
@@ -511,9 +564,9 @@ void oracle_jtv(const double *u, const double *wv, int H, int W, double lam,
             double gx = 0.5 * (v[(size_t)y * W + refl(x + 1, W)] - v[(size_t)y * W + refl(x - 1, W)]);
             double gy = 0.5 * (v[(size_t)refl(y + 1, H) * W + x] - v[(size_t)refl(y - 1, H) * W + x]);
             double d[16], e, q[2], de;
-            oracle_tensor(gx, gy, lam, d);
+            oracle_tensor(gx, gy, lam, diff, mu3, d);
             contract(d, Aw + 4 * i, T + 4 * i);        /* D is major-symmetric */
-            oracle_e_grad(gx, gy, Aw + 4 * i, Hu + 4 * i, lam, &e, q, &de);
+            oracle_e_grad(gx, gy, Aw + 4 * i, Hu + 4 * i, lam, diff, mu3, &e, q, &de);
             qx[i] = q[0]; qy[i] = q[1];
             dl += de;
         }
@@ -539,8 +592,8 @@ void oracle_jtv(const double *u, const double *wv, int H, int W, double lam,
  * gf = dL/df (zero off the mask), ginit = dL/du_init (zero on the mask),
  * glam[b] = dL/dlambda contributed by image b. */
 void oracle_backward(const double *ckpt, const uint8_t *mask, const double *f,
-                     int B, int H, int W, double lam, double sigma, double tau,
-                     int n, int M, const double *gu, double *gf, double *ginit,
+                     int B, int H, int W, double lam, double sigma, int diff, int mu3,
+                     double tau, int n, int M, const double *gu, double *gf, double *ginit,
                      double *glam)
 {
     size_t N = (size_t)H * W;
@@ -561,7 +614,7 @@ void oracle_backward(const double *ckpt, const uint8_t *mask, const double *f,
             memcpy(U, ckpt + ((size_t)m * B + b) * N, sizeof(double) * N);
             for (int k = 0; k < n; ++k)
                 oracle_step(U + (size_t)k * N, U + (size_t)(k > 0 ? k - 1 : 0) * N, mb, fb,
-                            H, W, lam, sigma, tau, k, U + (size_t)(k + 1) * N);
+                            H, W, lam, sigma, diff, mu3, tau, k, U + (size_t)(k + 1) * N);
             /* abar index j holds ubar^{m, j-1} */
             memset(abar, 0, sizeof(double) * N * (size_t)(n + 2));
             memcpy(abar + (size_t)(n + 1) * N, cyc, sizeof(double) * N);
@@ -574,7 +627,7 @@ void oracle_backward(const double *ckpt, const uint8_t *mask, const double *f,
                     if (mb[i]) { gfb[i] += an[i]; r[i] = 0.0; }
                     else r[i] = an[i];
                 }
-                oracle_jtv(U + (size_t)k * N, r, H, W, lam, sigma, jt, &dl);
+                oracle_jtv(U + (size_t)k * N, r, H, W, lam, sigma, diff, mu3, jt, &dl);
                 for (size_t i = 0; i < N; ++i) {
                     ac[i] += a * r[i] - tau * a * jt[i];
                     ap[i] += (1.0 - a) * r[i];

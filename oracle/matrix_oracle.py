@@ -70,10 +70,34 @@ def derivative_matrices(H: int, W: int):
     return Dx, Dy, Bxx, Byy, Bxy
 
 
-def mandel_tensor(gx: float, gy: float, lam: float) -> np.ndarray:
-    """3x3 Mandel form of sum_i mu_i E_i (x) E_i with mu = (g, 1, sqrt g)."""
+def diffusivity(s2: float, lam: float, diff: int = 0) -> float:
+    """Table 7 diffusivities of t = s^2/lambda^2: Charbonnier (1+t)^-1/2,
+    Perona-Malik (1+t)^-1, exponential Perona-Malik e^-t, Geman-Reynolds
+    (1+t)^-2 (the table's 2 lambda^2/(s^2+lambda^2)^2 scaled to g(0) = 1)."""
+    t = s2 / (lam * lam)
+    if diff == 1:
+        return 1.0 / (1.0 + t)
+    if diff == 2:
+        return math.exp(-t)
+    if diff == 3:
+        return 1.0 / (1.0 + t) ** 2
+    return 1.0 / math.sqrt(1.0 + t)
+
+
+def mu3_rule(mu1: float, mu2: float, rule: int = 0) -> float:
+    """mu_3 as a mean of mu_1 and mu_2 (Sec. 3.1, Table 1): geometric
+    (FOEED), arithmetic, or the maximum."""
+    if rule == 1:
+        return 0.5 * (mu1 + mu2)
+    if rule == 2:
+        return max(mu1, mu2)
+    return math.sqrt(mu1 * mu2)
+
+
+def mandel_tensor(gx: float, gy: float, lam: float, diff: int = 0, mu3: int = 0) -> np.ndarray:
+    """3x3 Mandel form of sum_i mu_i E_i (x) E_i with mu = (g, 1, mu_3(g, 1))."""
     s2 = gx * gx + gy * gy
-    g = 1.0 / math.sqrt(1.0 + s2 / (lam * lam))
+    g = diffusivity(s2, lam, diff)
     if s2 > 0:
         s = math.sqrt(s2)
         c, sn = gx / s, gy / s
@@ -83,10 +107,11 @@ def mandel_tensor(gx: float, gy: float, lam: float) -> np.ndarray:
     e1 = np.array([c * c, sn * sn, r2 * c * sn])
     e2 = np.array([sn * sn, c * c, -r2 * c * sn])
     e3 = np.array([-r2 * c * sn, r2 * c * sn, c * c - sn * sn])
-    return g * np.outer(e1, e1) + np.outer(e2, e2) + math.sqrt(g) * np.outer(e3, e3)
+    return (g * np.outer(e1, e1) + np.outer(e2, e2)
+            + mu3_rule(g, 1.0, mu3) * np.outer(e3, e3))
 
 
-def P_matrix(u: np.ndarray, lam: float, sigma: float) -> np.ndarray:
+def P_matrix(u: np.ndarray, lam: float, sigma: float, diff: int = 0, mu3: int = 0) -> np.ndarray:
     """Dense P(u) = B^T M(u) B for an H x W image u."""
     H, W = u.shape
     N = H * W
@@ -98,13 +123,13 @@ def P_matrix(u: np.ndarray, lam: float, sigma: float) -> np.ndarray:
     P = np.zeros((N, N))
     for p in range(N):
         Bp = np.stack([Bxx[p], Byy[p], r2 * Bxy[p]])
-        P += Bp.T @ mandel_tensor(gx[p], gy[p], lam) @ Bp
+        P += Bp.T @ mandel_tensor(gx[p], gy[p], lam, diff, mu3) @ Bp
     return P
 
 
-def F(u: np.ndarray, lam: float, sigma: float) -> np.ndarray:
+def F(u: np.ndarray, lam: float, sigma: float, diff: int = 0, mu3: int = 0) -> np.ndarray:
     """F(u) = P(u) u."""
-    return (P_matrix(u, lam, sigma) @ u.reshape(-1)).reshape(u.shape)
+    return (P_matrix(u, lam, sigma, diff, mu3) @ u.reshape(-1)).reshape(u.shape)
 
 
 def biharmonic_symbol(H: int, W: int) -> np.ndarray:
