@@ -83,14 +83,44 @@ extern "C" {
  * All strip shapes give bitwise the same results; so do all tile shapes. */
 #define EED4_FORCE_SHAPE(s)  ((((s) + 1) & 0xff) << 8)
 
+/* Tensor variants.  The default (both fields 0) is the paper's FOEED tensor:
+ * Charbonnier diffusivity and mu_3 = sqrt(mu_1 mu_2).  The others are the
+ * alternatives the paper compares: the diffusivities of Table 7 and the
+ * choices of mu_3 of Sec. 3.1 (Table 1).  With s = |grad u_sigma| and
+ * x = (s/lambda)^2, the diffusivity g = mu_1 is
+ *   EED4_CHARBONNIER       (1 + x)^(-1/2)   (eq. CharDiff)
+ *   EED4_PERONA_MALIK      (1 + x)^(-1)
+ *   EED4_PERONA_MALIK_EXP  exp(-x)
+ *   EED4_GEMAN_REYNOLDS    (1 + x)^(-2): Table 7's 2 lambda^2/(s^2+lambda^2)^2
+ *                          scaled to g(0) = 1 like the others
+ * (Table 7's Aubert entry vanishes at s = 0 and is not offered), and mu_3 is
+ *   EED4_MU3_GEOMETRIC     sqrt(mu_1 mu_2) = sqrt(g)
+ *   EED4_MU3_ARITHMETIC    (mu_1 + mu_2)/2 = (1 + g)/2
+ *   EED4_MU3_MAX           max(mu_1, mu_2) = 1.
+ * Every eigenvalue stays in [0, 1], so the step bound tau <= 1/16 holds for
+ * all of them.  A non-default variant runs the 60-column strip kernel of
+ * shape 5 (EED4_FORCE_SHAPE may name only that shape; EED4_TILE_KERNEL is
+ * EED4_EINVAL) and is available in eed4_inpaint, eed4_fsi_cycle and
+ * eed4_fsi_step; eed4_backward and the batched entry points accept only the
+ * default (EED4_EINVAL otherwise). */
+#define EED4_CHARBONNIER       0
+#define EED4_PERONA_MALIK      1
+#define EED4_PERONA_MALIK_EXP  2
+#define EED4_GEMAN_REYNOLDS    3
+#define EED4_MU3_GEOMETRIC     0
+#define EED4_MU3_ARITHMETIC    1
+#define EED4_MU3_MAX           2
+#define EED4_DIFFUSIVITY(d)  (((d) & 0xf) << 16)
+#define EED4_MU3(r)          (((r) & 0x3) << 20)
+
 /* ---- workspace sizing (eed4_workspace_size op) ---- */
 #define EED4_OP_INPAINT  1
 #define EED4_OP_CYCLE    2
 #define EED4_OP_BACKWARD 3
 
 typedef struct eed4_params {
-    float lambda;    /* contrast lambda > 0 of the Charbonnier diffusivity
-                        g(s^2) = 1/sqrt(1 + s^2/lambda^2) (eq. CharDiff)        */
+    float lambda;    /* contrast lambda > 0 of the diffusivity; by default the
+                        Charbonnier g(s^2) = 1/sqrt(1 + s^2/lambda^2) (eq. CharDiff) */
     float sigma;     /* presmoothing sigma >= 0 with ceil(3 sigma) <= 8; 0 disables
                         the presmoothing (Sec. 2.2)                            */
     float tau;       /* time step tau in (0, 1/16] (Sec. 3.3)                   */

@@ -23,7 +23,10 @@ import torch
 from . import _lib
 from ._lib import (EED4_ABS_TOL, EED4_ALLOW_LARGE_TAU, EED4_FORCE_SHAPE, EED4_NO_GRAPH,
                    EED4_OP_BACKWARD, EED4_TILE_KERNEL, SHAPE_NAMES,
-                   EED4_OP_CYCLE, EED4_OP_INPAINT, eed4_image, eed4_params, eed4_stats)
+                   EED4_OP_CYCLE, EED4_OP_INPAINT, eed4_image, eed4_params, eed4_stats,
+                   EED4_CHARBONNIER, EED4_PERONA_MALIK, EED4_PERONA_MALIK_EXP, EED4_GEMAN_REYNOLDS,
+                   EED4_MU3_GEOMETRIC, EED4_MU3_ARITHMETIC, EED4_MU3_MAX, EED4_DIFFUSIVITY,
+                   EED4_MU3, DIFFUSIVITY_NAMES, MU3_NAMES)
 
 _lib.lib()  # fail loudly at import if libeed4.so is missing
 
@@ -33,6 +36,9 @@ __all__ = [
     "eed4_strerror", "EED4_ABS_TOL", "EED4_ALLOW_LARGE_TAU", "EED4_NO_GRAPH", "EED4_TILE_KERNEL",
     "EED4_OP_INPAINT", "EED4_OP_CYCLE", "EED4_OP_BACKWARD", "EED4_FORCE_SHAPE", "SHAPE_NAMES",
     "eed4_autotune_batched", "eed4_step_shape", "library_path",
+    "EED4_CHARBONNIER", "EED4_PERONA_MALIK", "EED4_PERONA_MALIK_EXP", "EED4_GEMAN_REYNOLDS",
+    "EED4_MU3_GEOMETRIC", "EED4_MU3_ARITHMETIC", "EED4_MU3_MAX", "EED4_DIFFUSIVITY", "EED4_MU3",
+    "DIFFUSIVITY_NAMES", "MU3_NAMES",
 ]
 
 

@@ -25,6 +25,26 @@ def EED4_FORCE_SHAPE(s):
     return ((s + 1) & 0xFF) << 8
 
 
+# tensor variants (diffusivities of Table 7, mu3 choices of Sec. 3.1)
+EED4_CHARBONNIER = 0
+EED4_PERONA_MALIK = 1
+EED4_PERONA_MALIK_EXP = 2
+EED4_GEMAN_REYNOLDS = 3
+EED4_MU3_GEOMETRIC = 0
+EED4_MU3_ARITHMETIC = 1
+EED4_MU3_MAX = 2
+DIFFUSIVITY_NAMES = ("charbonnier", "perona_malik", "perona_malik_exp", "geman_reynolds")
+MU3_NAMES = ("geometric", "arithmetic", "max")
+
+
+def EED4_DIFFUSIVITY(d):
+    return (d & 0xF) << 16
+
+
+def EED4_MU3(r):
+    return (r & 0x3) << 20
+
+
 SHAPE_NAMES = ("tile64x32", "tile64x16", "tile32x32", "strip", "strip_tall", "strip_short",
                "strip_tiny", "strip_wide", "strip_wide_short")
 

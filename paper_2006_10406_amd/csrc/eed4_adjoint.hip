@@ -909,6 +909,7 @@ extern "C" int eed4_backward(const float *ckpt, const uint8_t *mask, const float
 {
     int rc = check_params(p, B, H, W);
     if (rc != EED4_OK) return rc;
+    if (model_of_flags(p->flags) != 0) return EED4_EINVAL;   // adjoint of the FOEED tensor only
     if (!ckpt || !mask || !known || !grad_u || !grad_known || !grad_init || !grad_lambda || M < 1)
         return EED4_EINVAL;
     const int n = p->cycle_len, R = eed4_radius(p->sigma);

@@ -38,12 +38,19 @@ int check_params(const eed4_params *p, int B, int H, int W)
     if (!(p->tau > 0.0f) || !std::isfinite(p->tau)) return EED4_EINVAL;
     if (p->cycle_len < 1 || p->max_cycles < 1) return EED4_EINVAL;
     if (!(p->tol >= 0.0f) || !std::isfinite(p->tol)) return EED4_EINVAL;
-    if (((p->flags >> 8) & 0xff) > kNumShapes) return EED4_EINVAL;
+    const int forced = (p->flags >> 8) & 0xff;
+    if (forced > kNumShapes) return EED4_EINVAL;
+    if (((p->flags >> 16) & 0xf) >= kNumDiffusivities || ((p->flags >> 20) & 0x3) >= kNumMu3Rules)
+        return EED4_EINVAL;
+    // a tensor variant runs one kernel shape (the 28-row strips)
+    if (model_of_flags(p->flags) != 0 &&
+        ((forced && forced - 1 != kShapeStripShort) || (p->flags & EED4_TILE_KERNEL)))
+        return EED4_EINVAL;
     if (!(p->flags & EED4_ALLOW_LARGE_TAU) && (double)p->tau > 1.0 / 16.0) return EED4_EUNSTABLE;
     return EED4_OK;
 }
 
-StepArgs make_args(float sigma, int R, float tau, float lambda, int k)
+StepArgs make_args(float sigma, int R, float tau, float lambda, int k, int model)
 {
     StepArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -60,6 +67,7 @@ StepArgs make_args(float sigma, int R, float tau, float lambda, int k)
     a.tau = tau;
     a.alpha = (float)((4.0 * k + 2.0) / (2.0 * k + 3.0));
     a.inv_lam2 = (float)(1.0 / ((double)lambda * (double)lambda));
+    a.model = model;
     return a;
 }
 
@@ -110,7 +118,7 @@ int enqueue_cycle(const CycleJob &j, hipStream_t s)
         float *cur, *prev, *out;
         cycle_roles(k, n, j.S, j.X, j.Y, &cur, &prev, &out);
         const bool last = (k == n - 1);
-        StepArgs a = make_args(j.sigma, j.R, j.tau, j.lambda, k);
+        StepArgs a = make_args(j.sigma, j.R, j.tau, j.lambda, k, j.model);
         hipError_t e = launch_step(j.R, j.shape, cur, prev, out, last ? j.S : nullptr, j.mask,
                                    j.B, j.H, j.W, a, last ? j.partials : nullptr, s);
         if (e != hipSuccess) return hip_fail(e, "fsi step launch");
@@ -244,6 +252,7 @@ std::string single_tune_key(int R, int B, int H, int W)
 // shapes; strips and tiles agree to rounding.
 int step_shape(const eed4_params *p, int B, int H, int W)
 {
+    if (model_of_flags(p->flags) != 0) return kShapeStripShort;   // the variant kernel
     const int forced = (p->flags >> 8) & 0xff;
     if (forced >= 1 && forced <= kNumShapes) return forced - 1;
     if (p->flags & EED4_TILE_KERNEL) return 0;
@@ -334,7 +343,8 @@ size_t eed4_workspace_size(int op, int B, int H, int W, const eed4_params *p)
     if (((p->flags >> 8) & 0xff) > kNumShapes) return 0;
     if (op == EED4_OP_INPAINT || op == EED4_OP_CYCLE)
         return inpaint_layout(op, B, H, W, eed4_radius(p->sigma), p->max_cycles).total;
-    if (op == EED4_OP_BACKWARD) return backward_workspace(B, H, W, p);
+    if (op == EED4_OP_BACKWARD)
+        return model_of_flags(p->flags) != 0 ? 0 : backward_workspace(B, H, W, p);
     return 0;
 }
 
@@ -355,13 +365,13 @@ int eed4_inpaint(float *u, const uint8_t *mask, const float *known, int B, int H
     CycleJob j;
     j.S = u; j.X = (float *)(base + L.X); j.Y = (float *)(base + L.Y);
     j.mask = mask; j.B = B; j.H = H; j.W = W; j.R = R; j.shape = step_shape(p, B, H, W); j.n = p->cycle_len;
-    j.sigma = p->sigma; j.tau = p->tau; j.lambda = p->lambda;
+    j.sigma = p->sigma; j.tau = p->tau; j.lambda = p->lambda; j.model = model_of_flags(p->flags);
     j.partials = (double *)(base + L.partials); j.sums = (double *)(base + L.sums);
     double *hist_dev = (double *)(base + L.hist);
 
     hipError_t e = launch_hold(u, mask, known, N, s);
     if (e != hipSuccess) return hip_fail(e, "hold launch");
-    if (!((p->flags >> 8) & 0xff) && !(p->flags & EED4_TILE_KERNEL) &&
+    if (!((p->flags >> 8) & 0xff) && !(p->flags & EED4_TILE_KERNEL) && j.model == 0 &&
         !tune_lookup(single_tune_key(R, B, H, W), &j.shape)) {
         if ((rc = tune_single_step(p, B, H, W, u, j.X, mask, s, &j.shape)) != EED4_OK) return rc;
     }
@@ -440,6 +450,7 @@ int eed4_fsi_cycle(float *u, const uint8_t *mask, const float *known, int B, int
     j.S = u; j.X = (float *)(base + L.X); j.Y = (float *)(base + L.Y);
     j.mask = mask; j.B = B; j.H = H; j.W = W; j.R = eed4_radius(p->sigma); j.shape = step_shape(p, B, H, W);
     j.n = p->cycle_len; j.sigma = p->sigma; j.tau = p->tau; j.lambda = p->lambda;
+    j.model = model_of_flags(p->flags);
     j.partials = (double *)(base + L.partials); j.sums = d_sums;
     hipError_t e = launch_hold(u, mask, known, (size_t)B * H * W, s);
     if (e != hipSuccess) return hip_fail(e, "hold launch");
@@ -456,7 +467,7 @@ int eed4_fsi_step(const float *ucur, const float *uprev, float *uout, const uint
     const char *c0 = (const char *)ucur, *o0 = (const char *)uout;
     if (o0 < c0 + bytes && c0 < o0 + bytes) return EED4_EINVAL;
     const int R = eed4_radius(p->sigma);
-    StepArgs a = make_args(p->sigma, R, p->tau, p->lambda, k);
+    StepArgs a = make_args(p->sigma, R, p->tau, p->lambda, k, model_of_flags(p->flags));
     hipError_t e = launch_step(R, step_shape(p, B, H, W), ucur, uprev, uout, nullptr, mask, B, H, W, a, nullptr,
                                (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "fsi step launch");

@@ -276,6 +276,7 @@ static BatchLayout batch_layout(const eed4_image *im, int B, const eed4_params *
 static int check_images(const eed4_image *im, int B, const eed4_params *p)
 {
     if (!im || B < 1 || !p) return EED4_EINVAL;
+    if (model_of_flags(p->flags) != 0) return EED4_EINVAL;   // FOEED tensor only
     for (int i = 0; i < B; ++i) {
         if (!im[i].u || !im[i].mask || !im[i].known) return EED4_EINVAL;
         eed4_params q = *p;

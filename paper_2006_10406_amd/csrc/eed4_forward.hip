@@ -34,12 +34,14 @@ __global__ __launch_bounds__(256) void step_kernel(const float *ucur, const floa
                          partials ? partials + 2 * (size_t)tile : nullptr);
 }
 
-template <int R, bool RES, int ROWS, int CPL>
-__global__ __launch_bounds__(256) void strip_kernel(const float *ucur, const float *uprev,
-                                                    float *uout, const float *ref,
-                                                    const uint8_t *__restrict__ mask, int H, int W,
-                                                    int nstrip, int per_img, int nitems, StepArgs a,
-                                                    double *partials)
+// Fused step over wave strips.  GEN selects the tensor variant at run time
+// (StepArgs::model); without it the kernel is the FOEED tensor.
+template <int R, bool RES, int ROWS, int CPL, bool GEN>
+__device__ __forceinline__ void strip_kernel_body(const float *ucur, const float *uprev,
+                                                  float *uout, const float *ref,
+                                                  const uint8_t *__restrict__ mask, int H, int W,
+                                                  int nstrip, int per_img, int nitems,
+                                                  const StepArgs &a, double *partials)
 {
     using G = StripGeo<R, ROWS, CPL>;
     __shared__ float lds[4 * G::LDS];
@@ -64,8 +66,33 @@ __global__ __launch_bounds__(256) void strip_kernel(const float *ucur, const flo
     s.tau = a.tau;
     s.alpha = a.alpha;
     s.il2q = 0.25f * a.inv_lam2;
-    strip_step<R, RES, ROWS, CPL>(lds + wave * G::LDS, s, a.w,
-                             RES ? partials + 2 * (size_t)item : nullptr);
+    s.model = a.model;
+    strip_step<R, RES, ROWS, CPL, GEN>(lds + wave * G::LDS, s, a.w,
+                                       RES ? partials + 2 * (size_t)item : nullptr);
+}
+
+template <int R, bool RES, int ROWS, int CPL>
+__global__ __launch_bounds__(256) void strip_kernel(const float *ucur, const float *uprev,
+                                                    float *uout, const float *ref,
+                                                    const uint8_t *__restrict__ mask, int H, int W,
+                                                    int nstrip, int per_img, int nitems, StepArgs a,
+                                                    double *partials)
+{
+    strip_kernel_body<R, RES, ROWS, CPL, false>(ucur, uprev, uout, ref, mask, H, W, nstrip,
+                                                per_img, nitems, a, partials);
+}
+
+// The tensor variants (diffusivities of Table 7, mu3 choices of Sec. 3.1) on
+// 60-column strips of >= 28 rows.
+template <int R, bool RES>
+__global__ __launch_bounds__(256) void strip_model_kernel(const float *ucur, const float *uprev,
+                                                          float *uout, const float *ref,
+                                                          const uint8_t *__restrict__ mask, int H,
+                                                          int W, int nstrip, int per_img,
+                                                          int nitems, StepArgs a, double *partials)
+{
+    strip_kernel_body<R, RES, 28, 1, true>(ucur, uprev, uout, ref, mask, H, W, nstrip, per_img,
+                                           nitems, a, partials);
 }
 
 // sums[b] = fixed-order sum of the residual partials of image b's tiles.
@@ -141,7 +168,7 @@ int tiles_per_image(int shape, int R, int H, int W)
     return ((W + ts.tw - 1) / ts.tw) * ((H + ts.th - 1) / ts.th);
 }
 
-template <int R, int ROWS, int CPL = 1>
+template <int R, int ROWS, int CPL = 1, bool GEN = false>
 static hipError_t launch_strip_t(const float *ucur, const float *uprev, float *uout,
                                  const float *ref, const uint8_t *mask, int B, int H, int W,
                                  const StepArgs &a, double *partials, hipStream_t s)
@@ -152,12 +179,25 @@ static hipError_t launch_strip_t(const float *ucur, const float *uprev, float *u
     const long long nitems = (long long)per_img * B;
     const long long nblk = (nitems + 3) / 4;
     if (nitems <= 0 || nblk > 0x7fffffffLL) return hipErrorInvalidValue;
-    if (ref)
-        hipLaunchKernelGGL((strip_kernel<R, true, ROWS, CPL>), dim3((unsigned)nblk), dim3(256), 0, s, ucur,
-                           uprev, uout, ref, mask, H, W, nstrip, per_img, (int)nitems, a, partials);
-    else
-        hipLaunchKernelGGL((strip_kernel<R, false, ROWS, CPL>), dim3((unsigned)nblk), dim3(256), 0, s, ucur,
-                           uprev, uout, ref, mask, H, W, nstrip, per_img, (int)nitems, a, partials);
+    static_assert(!GEN || (ROWS == 28 && CPL == 1), "tensor variants run 28-row strips");
+    if constexpr (GEN) {
+        if (ref)
+            hipLaunchKernelGGL((strip_model_kernel<R, true>), dim3((unsigned)nblk), dim3(256), 0, s,
+                               ucur, uprev, uout, ref, mask, H, W, nstrip, per_img, (int)nitems, a,
+                               partials);
+        else
+            hipLaunchKernelGGL((strip_model_kernel<R, false>), dim3((unsigned)nblk), dim3(256), 0, s,
+                               ucur, uprev, uout, ref, mask, H, W, nstrip, per_img, (int)nitems, a,
+                               partials);
+    } else if (ref) {
+        hipLaunchKernelGGL((strip_kernel<R, true, ROWS, CPL>), dim3((unsigned)nblk), dim3(256), 0, s,
+                           ucur, uprev, uout, ref, mask, H, W, nstrip, per_img, (int)nitems, a,
+                           partials);
+    } else {
+        hipLaunchKernelGGL((strip_kernel<R, false, ROWS, CPL>), dim3((unsigned)nblk), dim3(256), 0, s,
+                           ucur, uprev, uout, ref, mask, H, W, nstrip, per_img, (int)nitems, a,
+                           partials);
+    }
     return hipGetLastError();
 }
 
@@ -180,6 +220,11 @@ static hipError_t launch_step_r(int shape, const float *ucur, const float *uprev
                                 const float *ref, const uint8_t *mask, int B, int H, int W,
                                 const StepArgs &a, double *partials, hipStream_t s)
 {
+    // tensor variants: one kernel shape (60-column strips of >= 28 rows)
+    if (a.model != 0)
+        return shape == kShapeStripShort
+                   ? launch_strip_t<R, 28, 1, true>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s)
+                   : hipErrorInvalidValue;
     switch (shape) {
     case 0: return launch_step_t<R, 64, 32>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
     case 1: return launch_step_t<R, 64, 16>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);

@@ -15,6 +15,7 @@ struct CycleJob {
     const uint8_t *mask;
     int B, H, W, R, shape, n;
     float sigma, tau, lambda;
+    int model;                 // tensor variant (0: FOEED)
     double *partials;          // per-tile residual partials
     double *sums;              // [B][2] residual sums
 };
@@ -52,7 +53,7 @@ void tune_remember(const std::string &key, int shape);
 std::string single_tune_key(int R, int B, int H, int W);
 int tune_single_step(const eed4_params *p, int B, int H, int W, float *S, float *X,
                      const uint8_t *mask, hipStream_t s, int *shape);
-StepArgs make_args(float sigma, int R, float tau, float lambda, int k);
+StepArgs make_args(float sigma, int R, float tau, float lambda, int k, int model = 0);
 hipStream_t capture_stream();
 hipStream_t recompute_stream();
 void cycle_roles(int k, int n, float *S, float *X, float *Y, float **cur, float **prev,

@@ -17,7 +17,15 @@ struct StepArgs {
     float tau;               // time step
     float alpha;             // FSI weight alpha_k = (4k+2)/(2k+3)
     float inv_lam2;          // 1 / lambda^2
+    int model;               // tensor variant: diffusivity | mu3 rule << 4 (0: FOEED)
 };
+
+// Tensor variants (the public flags EED4_DIFFUSIVITY / EED4_MU3).
+constexpr int kNumDiffusivities = 4;   // Charbonnier, Perona-Malik, exp. Perona-Malik, Geman-Reynolds
+constexpr int kNumMu3Rules = 3;        // geometric mean, arithmetic mean, maximum
+constexpr int kDiffPeronaMalik = 1, kDiffPeronaMalikExp = 2, kDiffGemanReynolds = 3;
+constexpr int kMu3Arithmetic = 1, kMu3Max = 2;
+inline int model_of_flags(int flags) { return ((flags >> 16) & 0xf) | (((flags >> 20) & 0x3) << 4); }
 
 // Output tile of the fused step kernels.
 struct TileShape {

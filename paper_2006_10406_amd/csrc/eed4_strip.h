@@ -93,7 +93,33 @@ struct StripArgs {
     const uint8_t *mask;
     int H, W, X0, Y0;
     float tau, alpha, il2q;     // il2q = 1 / (4 lambda^2)
+    int model;                  // tensor variant (GEN kernels only)
 };
+
+// mu1 = g(x) and mu3 of the tensor variants, x = (s/lambda)^2: the
+// diffusivities of Table 7 (Geman-Reynolds scaled to g(0) = 1) and the mu3
+// choices of Sec. 3.1 (geometric mean, arithmetic mean or maximum of mu1 and
+// mu2 = 1).  model = diffusivity | rule << 4, uniform over the launch.
+__device__ __forceinline__ void model_mu(float x, int model, float &mu1, float &mu3)
+{
+    const int diff = model & 0xf, rule = model >> 4;
+    const float d = 1.0f + x;
+    float g;
+    if (diff == kDiffPeronaMalik) {
+        g = __builtin_amdgcn_rcpf(d);
+    } else if (diff == kDiffPeronaMalikExp) {
+        g = expf(-x);
+    } else if (diff == kDiffGemanReynolds) {
+        const float r = __builtin_amdgcn_rcpf(d);
+        g = r * r;
+    } else {
+        g = __builtin_amdgcn_rsqf(d);
+    }
+    mu1 = g;
+    mu3 = rule == kMu3Arithmetic ? 0.5f * (1.0f + g)
+        : rule == kMu3Max        ? 1.0f
+                                 : __builtin_amdgcn_sqrtf(g);
+}
 
 // Raw buffer resource over the `bytes` bytes from `base` (gfx9 descriptor:
 // stride 0, no swizzle).  A load at a byte offset at or beyond `bytes` reads 0
@@ -157,7 +183,7 @@ __device__ __forceinline__ float right_of(const float (&x)[CPL], int q)
 // covering nb = min(H - b0, NROW) rows, so a row offset is one 32-bit scalar
 // (the library keeps NROW * W * 4 below 2^31) and the per-lane column offsets
 // stay fixed for the whole strip.
-template <int R, bool RES, int ROWS = 64, int CPL = 1>
+template <int R, bool RES, int ROWS = 64, int CPL = 1, bool GEN = false>
 __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
                                            const float (&w)[2 * kRMax + 1], double *partial)
 {
@@ -305,8 +331,13 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
                 const float hxy = 0.25f * ((up[CS] + um[-CS]) - (up[-CS] + um[CS]));
 
                 const float s2 = fmaf(gxs, gxs, gys * gys);                  // 4 |grad|^2
-                const float mu1 = __builtin_amdgcn_rsqf(fmaf(s2, s.il2q, 1.0f));
-                const float mu3 = __builtin_amdgcn_sqrtf(mu1);
+                float mu1, mu3;
+                if constexpr (GEN) {
+                    model_mu(s2 * s.il2q, s.model, mu1, mu3);
+                } else {                                     // FOEED: Charbonnier, sqrt
+                    mu1 = __builtin_amdgcn_rsqf(fmaf(s2, s.il2q, 1.0f));
+                    mu3 = __builtin_amdgcn_sqrtf(mu1);
+                }
                 const float rn = __builtin_amdgcn_rsqf(fmaxf(s2, 1e-30f));
                 const float nx = gxs * rn, ny = gys * rn;   // unit direction (0 where grad = 0)
                 const float aa = nx * nx, bb = ny * ny, c = nx * ny;

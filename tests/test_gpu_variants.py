@@ -1,0 +1,106 @@
+"""Parity of the tensor variants (diffusivities of Table 7, mu3 choices of
+Sec. 3.1) on the GPU with the FP64 oracle, through the C ABI.
+
+Same bar as the FOEED tensor: relative L2 <= 1e-5 for one FSI cycle started
+from the oracle's state, RMSE <= 1e-4 for multi-cycle runs at equal cycle
+counts.  Sizes span several strips and segments with ragged tails.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth import make_problem
+from tests.helpers import REL_L2_PER_CYCLE, RMSE_STEADY, announce, rel_l2, rmse, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+import paper_2006_10406_amd as eed4  # noqa: E402
+
+COMBOS = [(d, r) for d in range(len(eed4.DIFFUSIVITY_NAMES)) for r in range(len(eed4.MU3_NAMES))]
+
+
+def flags_of(d, r):
+    return eed4.EED4_DIFFUSIVITY(d) | eed4.EED4_MU3(r)
+
+
+def label(d, r):
+    return f"{eed4.DIFFUSIVITY_NAMES[d]}/{eed4.MU3_NAMES[r]}"
+
+
+@pytest.mark.parametrize("d,r", COMBOS)
+def test_per_cycle_parity(d, r):
+    H, W, lam, sigma, tau, n, M = 96, 130, 0.04, 1.0, 0.05, 10, 3
+    announce(f"variant {label(d, r)}: per-cycle parity {H}x{W}, {M} cycles of {n}")
+    pr = make_problem(H, W, 12, True, 0.01, 0.05, 700 + 3 * d + r)
+    _, _, _, ck = oracle.inpaint(pr["u_init"], pr["mask"], pr["known"], lam, sigma, tau, n, M,
+                                 checkpoints=True, diff=d, mu3=r)
+    ck32 = ck.astype(np.float32)
+    masks = np.repeat(pr["mask"][None], M, 0)
+    knowns = np.repeat(pr["known"][None], M, 0).astype(np.float32)
+    u = to_dev(ck32)
+    sums = torch.zeros((M, 2), dtype=torch.float64, device="cuda")
+    p = eed4.params(lam, sigma, tau, n, 1, flags=flags_of(d, r))
+    if (d, r) != (0, 0):
+        assert eed4.eed4_step_shape(M, H, W, p) == 5          # the variant kernel
+    eed4.eed4_fsi_cycle(u, to_dev(masks), to_dev(knowns), p, sums)
+    torch.cuda.synchronize()
+    got = u.cpu().numpy()
+    ref, _, hist = oracle.inpaint(ck32.astype(np.float64), masks, knowns.astype(np.float64), lam,
+                                  sigma, tau, n, 1, diff=d, mu3=r)
+    errs = [rel_l2(got[m], ref[m]) for m in range(M)]
+    print(f"{label(d, r)} per-cycle rel L2 vs FP64: max {max(errs):.3e}")
+    assert max(errs) <= REL_L2_PER_CYCLE
+    assert np.allclose(np.sqrt(sums.cpu().numpy()[:, 1]), hist[0, :, 1], rtol=1e-6)
+    kn = masks != 0
+    assert np.array_equal(got[kn], knowns[kn])
+
+
+@pytest.mark.parametrize("d,r,sigma", [(2, 1, 2.0), (3, 2, 1.5), (1, 0, 0.5)])
+def test_full_run_equal_cycles(d, r, sigma):
+    H, W, lam, tau, n, M = 150, 200, 0.03, 0.05, 15, 8
+    announce(f"variant {label(d, r)}: eed4_inpaint {H}x{W} sigma {sigma}, {M} cycles of {n}")
+    pr = make_problem(H, W, 20, True, 0.005, 0.04, 800 + d)
+    ref, cyc, rh = oracle.inpaint(pr["u_init"], pr["mask"], pr["known"], lam, sigma, tau, n, M,
+                                  diff=d, mu3=r)
+    u = to_dev(pr["u_init"])
+    p = eed4.params(lam, sigma, tau, n, M, flags=flags_of(d, r))
+    st, hist = eed4.eed4_inpaint(u, to_dev(pr["mask"]), to_dev(pr["known"]), p, history=True)
+    got = u.cpu().numpy()
+    e = rmse(got, ref)
+    print(f"{label(d, r)} sigma {sigma}: RMSE vs FP64 after {st.cycles} cycles {e:.3e}; "
+          f"vs ground truth {rmse(got, pr['image']):.4f} (oracle {rmse(ref, pr['image']):.4f})")
+    assert st.cycles == cyc == M
+    assert e <= RMSE_STEADY
+    assert np.allclose(hist[:, 0, 1], rh[:, 1], rtol=1e-5)
+    assert eed4.eed4_step_shape(1, H, W, p) == 5
+
+
+def test_graph_and_direct_launches_agree():
+    d, r = 2, 0
+    H, W = 70, 190
+    announce(f"variant {label(d, r)}: hipGraph cycle vs direct launches, {H}x{W}")
+    pr = make_problem(H, W, 8, True, 0.01, 0.05, 901)
+    outs = []
+    for extra in (0, eed4.EED4_NO_GRAPH):
+        u = to_dev(pr["u_init"])
+        p = eed4.params(0.05, 1.0, 0.05, 10, 4, flags=flags_of(d, r) | extra)
+        eed4.eed4_inpaint(u, to_dev(pr["mask"]), to_dev(pr["known"]), p)
+        outs.append(u.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_variant_differs_from_foeed():
+    # the variant path is really taken: another diffusivity gives another result
+    H, W = 64, 90
+    announce(f"variant path taken: FOEED vs exponential Perona-Malik, {H}x{W}")
+    pr = make_problem(H, W, 8, True, 0.01, 0.05, 902)
+    outs = []
+    for fl in (0, flags_of(2, 0)):
+        u = to_dev(pr["u_init"])
+        eed4.eed4_inpaint(u, to_dev(pr["mask"]), to_dev(pr["known"]),
+                          eed4.params(0.05, 1.0, 0.05, 10, 3, flags=fl))
+        outs.append(u.cpu().numpy())
+    assert rel_l2(outs[0], outs[1]) > 1e-4
