@@ -17,6 +17,8 @@ The JSON line carries:
   cpu_baseline  the FP64 oracle on the host cores, one cycle of the same image
   adjoint_forward_ratio  backward/forward time on 16 x 256 x 256 (30 cycles of 10)
   batched    64 uneven images: one batched call vs 64 single-image calls
+  variants   fused step time of each tensor variant (Table 7 diffusivities,
+             Sec. 3.1 mu3 choices) on the workload image
 """
 import argparse
 import hashlib
@@ -200,11 +202,61 @@ def probe(eed4, torch, u_init, mask, wl):
                 eed4.eed4_fsi_step(cur, prev, out, mask, ps, k)
         torch.cuda.synchronize()
         log(f"probe: {name}")
+    # the tensor-variant kernel (one kernel serves every variant)
+    ps = eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, 1,
+                     flags=eed4.EED4_DIFFUSIVITY(eed4.EED4_PERONA_MALIK_EXP)
+                     | eed4.EED4_MU3(eed4.EED4_MU3_ARITHMETIC))
+    for _ in range(3):
+        for k in range(wl.n):
+            cur, prev, out = roles(k)
+            eed4.eed4_fsi_step(cur, prev, out, mask, ps, k)
+    torch.cuda.synchronize()
+    log("probe: tensor-variant kernel")
     src = torch.ones(16 << 20, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
     log(f"probe done: {3 * wl.n} step launches per shape, one copy of {src.numel() * 4} bytes")
+
+
+def variants_timing(eed4, torch, u, mask, wl, stream, reps=2):
+    """Fused step of every tensor variant (Table 7 diffusivity x Sec. 3.1 mu3 choice) on
+    the workload image, back-to-back launches on one stream, median of three windows.
+    The variants run strip_model_kernel<R, false> (60-column strips of >= 28 rows); the
+    FOEED default is the tuned kernel of the main measurement."""
+    H, W, n = wl.H, wl.W, wl.n
+    a, b, c = u.clone(), u.clone(), u.clone()
+    roles = lambda k: (a, a, b) if k == 0 else ((b, a, c) if k == 1 else
+                                                 ((b, c, c) if k % 2 else (c, b, b)))
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    R = eed4.eed4_radius(wl.sigma)
+    res = {"kernel": f"strip_model_kernel<{R}, false>", "unit": "us/launch",
+           "bytes_per_launch": BYTES_PER_UPDATE * H * W, "per_variant": {}}
+    for d, dn in enumerate(eed4.DIFFUSIVITY_NAMES):
+        for r, rn in enumerate(eed4.MU3_NAMES):
+            if d == 0 and r == 0:
+                continue
+            ps = eed4.params(wl.lam, wl.sigma, wl.tau, n, 1,
+                             flags=eed4.EED4_DIFFUSIVITY(d) | eed4.EED4_MU3(r))
+            for k in range(n):
+                cur, prev, out = roles(k)
+                eed4.eed4_fsi_step(cur, prev, out, mask, ps, k, stream=stream)
+            windows = []
+            for _ in range(3):
+                e0.record(stream)
+                for _ in range(reps):
+                    for k in range(n):
+                        cur, prev, out = roles(k)
+                        eed4.eed4_fsi_step(cur, prev, out, mask, ps, k, stream=stream)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                windows.append(e0.elapsed_time(e1) / (reps * n))
+            us = sorted(windows)[1] * 1e3
+            gbs = BYTES_PER_UPDATE * H * W / (us * 1e-6) / 1e9
+            res["per_variant"][f"{dn}/{rn}"] = {"us": round(us, 1),
+                                                "hbm_frac": round(gbs / HBM_PEAK_GBS, 3)}
+    return res
 
 
 def batched_vs_single(eed4, torch, cycles):
@@ -294,6 +346,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--batched-cycles", type=int, default=40)
     ap.add_argument("--adjoint-probe", action="store_true",
                     help="backward passes only (16 x 256x256 and one 4096x4096 cycle), for "
@@ -431,6 +484,9 @@ def main():
                      "kernel_source_sha": kernel_source_sha(),
                      "copy_context": copy_bandwidth(torch)},
     }
+    if not args.no_variants:
+        log("tensor variants (Table 7 diffusivities x mu3 choices)")
+        out["variants"] = variants_timing(eed4, torch, u, mask, wl, stream)
     if not args.no_adjoint:
         log("adjoint / forward timing (16 x 256x256)")
         out["adjoint_forward_ratio"] = adjoint_ratio(eed4, torch, args)

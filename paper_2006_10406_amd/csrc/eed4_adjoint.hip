@@ -864,35 +864,20 @@ static int adjoint_shape(const eed4_params *p, RevStep t, hipStream_t s, int *sh
     if (tune_lookup(key, shape)) return EED4_OK;
     // the wide forward shapes map onto the same reverse strips as their heights
     const int cands[] = {kShapeStrip, 0, kShapeStripTall, kShapeStripShort, kShapeStripTiny};
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t e = hipEventCreate(&e0);
-    if (e == hipSuccess) e = hipEventCreate(&e1);
     const size_t N = (size_t)t.B * t.H * t.W;
-    if (e == hipSuccess) e = launch_fill(t.ac, N, 0.0f, s);
-    int best = cands[0];
-    float bt = 1e30f;
-    for (int c : cands) {
-        if (e != hipSuccess) break;
-        t.shape = c;
-        t.first = 0;
-        float tmin = 1e30f;
-        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
-            e = hipEventRecord(e0, s);
-            if (e == hipSuccess) e = launch_reverse_step(t, p, p->cycle_len - 1, s);
-            if (e == hipSuccess) e = hipEventRecord(e1, s);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.0f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e == hipSuccess && rep > 0) tmin = std::fmin(tmin, ms);   // first run warms up
-        }
-        if (e == hipSuccess && tmin < kTuneMargin * bt) {
-            bt = tmin;
-            best = c;
-        }
-    }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
+    hipError_t e = launch_fill(t.ac, N, 0.0f, s);
     if (e != hipSuccess) return hip_fail(e, "adjoint autotune");
+    int best = cands[0];
+    const int rc = tune_pick(
+        cands, (int)(sizeof(cands) / sizeof(cands[0])), s,
+        [&](int c) {
+            t.shape = c;
+            t.first = 0;
+            return (int)EED4_OK;
+        },
+        [&](int) { return launch_reverse_step(t, p, p->cycle_len - 1, s); }, "adjoint autotune",
+        &best, nullptr);
+    if (rc != EED4_OK) return rc;
     tune_remember(key, best);
     *shape = best;
     return EED4_OK;

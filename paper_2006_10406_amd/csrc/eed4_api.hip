@@ -274,40 +274,15 @@ int tune_single_step(const eed4_params *p, int B, int H, int W, float *S, float 
                      const uint8_t *mask, hipStream_t s, int *shape)
 {
     const int R = eed4_radius(p->sigma);
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t e = hipEventCreate(&e0);
-    if (e == hipSuccess) e = hipEventCreate(&e1);
-    if (e != hipSuccess) {
-        if (e0) (void)hipEventDestroy(e0);
-        return hip_fail(e, "event");
-    }
     const StepArgs a = make_args(p->sigma, R, p->tau, p->lambda, 0);
     int order[kNumShapes];
     tune_order(default_step_shape(R, B, H, W), order);
-    int best = order[0];
-    float bt = 1e30f;
-    for (int sh : order) {
-        if (e != hipSuccess) break;
-        float tmin = 1e30f;
-        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
-            e = hipEventRecord(e0, s);
-            if (e == hipSuccess) e = launch_step(R, sh, S, S, X, nullptr, mask, B, H, W, a, nullptr, s);
-            if (e == hipSuccess) e = hipEventRecord(e1, s);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.0f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e == hipSuccess && rep > 0) tmin = std::fmin(tmin, ms);   // first run warms up
-        }
-        if (e == hipSuccess && tmin < kTuneMargin * bt) {
-            bt = tmin;
-            best = sh;
-        }
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (e != hipSuccess) return hip_fail(e, "step autotune");
-    *shape = best;
-    tune_remember(single_tune_key(R, B, H, W), best);
+    const int rc = tune_pick(
+        order, kNumShapes, s, [](int) { return (int)EED4_OK; },
+        [&](int sh) { return launch_step(R, sh, S, S, X, nullptr, mask, B, H, W, a, nullptr, s); },
+        "step autotune", shape, nullptr);
+    if (rc != EED4_OK) return rc;
+    tune_remember(single_tune_key(R, B, H, W), *shape);
     return EED4_OK;
 }
 

@@ -430,44 +430,23 @@ static std::string batch_tune_key(const eed4_image *im, int B, int R)
 static int autotune(const eed4_image *im, int B, const eed4_params *p, char *base,
                     const BatchLayout &L, hipStream_t s, int *best_shape, float *best_ms)
 {
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess) return hip_fail(hipErrorInvalidValue, "event");
-    if (hipEventCreate(&e1) != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        return hip_fail(hipErrorInvalidValue, "event");
-    }
     int order[kNumShapes];
     tune_order(kShapeStrip, order);
-    int best = kShapeStrip, rc = EED4_OK;
-    float bt = 1e30f;
-    for (int sh : order) {
-        if (rc != EED4_OK) break;
-        BatchRun r;
-        if ((rc = prepare(r, im, B, p, sh, base, L, s)) != EED4_OK) break;
-        StepArgs a = make_args(p->sigma, r.R, p->tau, 1.0f, 0);
-        float tmin = 1e30f;
-        for (int rep = 0; rep < 3 && rc == EED4_OK; ++rep) {
-            hipError_t e = hipEventRecord(e0, s);
-            if (e == hipSuccess)
-                e = launch_bstep(r.R, sh, r.grid, r.dimg, r.dqueue, r.dqlen, 0, 0, 1,
-                                 false, a, r.dpartials, s);
-            if (e == hipSuccess) e = hipEventRecord(e1, s);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.0f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) rc = hip_fail(e, "autotune timing");
-            else if (rep > 0) tmin = std::min(tmin, ms);   // first run warms up
-        }
-        if (rc == EED4_OK && tmin < kTuneMargin * bt) {
-            bt = tmin;
-            best = sh;
-        }
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    *best_shape = best;
-    *best_ms = bt;
-    return rc;
+    BatchRun r;
+    StepArgs a;
+    return tune_pick(
+        order, kNumShapes, s,
+        [&](int sh) {
+            r = BatchRun();
+            const int rc = prepare(r, im, B, p, sh, base, L, s);
+            a = make_args(p->sigma, r.R, p->tau, 1.0f, 0);
+            return rc;
+        },
+        [&](int sh) {
+            return launch_bstep(r.R, sh, r.grid, r.dimg, r.dqueue, r.dqlen, 0, 0, 1, false, a,
+                                r.dpartials, s);
+        },
+        "autotune timing", best_shape, best_ms);
 }
 
 static int choose_shape(const eed4_image *im, int B, const eed4_params *p, char *base,

@@ -4,6 +4,7 @@
 #include "eed4.h"
 #include "eed4_internal.h"
 
+#include <cmath>
 #include <functional>
 #include <string>
 
@@ -32,9 +33,9 @@ int step_shape(const eed4_params *p, int B, int H, int W);
 // chip), and strips otherwise.
 constexpr long long kMinStripWaves = 2048;
 
-// The autotuners time the default shape first and move to another only when
-// it is faster by more than this factor, so shapes within timing noise of each
-// other do not swap between runs.
+// The autotuners keep the default shape unless another is faster by more than
+// this factor, so shapes within timing noise of each other do not swap between
+// runs.
 constexpr float kTuneMargin = 0.98f;
 // Candidate order for a tuner: `first`, then the other shapes in index order.
 inline void tune_order(int first, int (&order)[kNumShapes])
@@ -45,6 +46,48 @@ inline void tune_order(int first, int (&order)[kNumShapes])
         if (sh != first) order[n++] = sh;
 }
 int default_step_shape(int R, int B, int H, int W);
+
+// Chooses one of n candidate shapes (cands[0] the default) by timing on stream
+// s.  prepare(shape) sets up a candidate outside the timed region (EED4 code);
+// launch(shape) enqueues one launch of it.  Every candidate is sampled in two
+// round-robin passes of one warm-up and two timed launches and keeps its
+// fastest time, so the clock ramp at the start of tuning does not favour the
+// candidates timed later.  A candidate replaces the current choice only when
+// it is faster by more than kTuneMargin.
+template <typename Prepare, typename Launch>
+int tune_pick(const int *cands, int n, hipStream_t s, Prepare &&prepare, Launch &&launch,
+              const char *where, int *best, float *best_ms)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float tmin[kNumShapes];
+    for (int i = 0; i < n; ++i) tmin[i] = 1e30f;
+    int rc = EED4_OK;
+    for (int pass = 0; pass < 2 && e == hipSuccess && rc == EED4_OK; ++pass)
+        for (int i = 0; i < n && e == hipSuccess && rc == EED4_OK; ++i) {
+            if ((rc = prepare(cands[i])) != EED4_OK) break;
+            for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+                e = hipEventRecord(e0, s);
+                if (e == hipSuccess) e = launch(cands[i]);
+                if (e == hipSuccess) e = hipEventRecord(e1, s);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.0f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e == hipSuccess && rep > 0) tmin[i] = std::fmin(tmin[i], ms);
+            }
+        }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (rc != EED4_OK) return rc;
+    if (e != hipSuccess) return hip_fail(e, where);
+    int b = 0;
+    for (int i = 1; i < n; ++i)
+        if (tmin[i] < kTuneMargin * tmin[b]) b = i;
+    *best = cands[b];
+    if (best_ms) *best_ms = tmin[b];
+    return EED4_OK;
+}
 
 // Autotuner choice cache (process-wide; persisted to the file named by
 // EED4_AUTOTUNE_CACHE when set).
