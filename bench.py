@@ -19,6 +19,7 @@ The JSON line carries:
   batched    64 uneven images: one batched call vs 64 single-image calls
   variants   fused step time of each tensor variant (Table 7 diffusivities,
              Sec. 3.1 mu3 choices) on the workload image
+  workloads  colour (channel-wise RGB) and scratch-removal inpainting, 512x512
 """
 import argparse
 import hashlib
@@ -259,6 +260,38 @@ def variants_timing(eed4, torch, u, mask, wl, stream, reps=2):
     return res
 
 
+def workload_throughput(eed4, torch, names=("rgb512", "scratch512_thin", "scratch512_thick")):
+    """Colour (channel-wise, a batch of 3 planes) and scratch-removal workloads through
+    eed4_inpaint: wl.M fixed cycles after a tuning call; pixel-updates/s counts every
+    channel's pixels."""
+    from synth import WORKLOADS, make_workload_problem
+    res = {}
+    for name in names:
+        wl = WORKLOADS[name]
+        pr = make_workload_problem(wl)
+        mask = torch.from_numpy(pr["mask"]).cuda()
+        known = torch.from_numpy(pr["known"]).cuda()
+        u0 = torch.from_numpy(pr["u_init"]).cuda()
+        u = u0.clone()
+        eed4.eed4_inpaint(u, mask, known, eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, 2))
+        p = eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, wl.M)
+        u = u0.clone()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        st, _ = eed4.eed4_inpaint(u, mask, known, p)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        px = u0.numel()
+        B = px // (wl.H * wl.W)
+        res[name] = {"mpix_updates_s": round(px * wl.n * st.cycles / (ms * 1e-3) / 1e6, 1),
+                     "ms": round(ms, 3), "cycles": st.cycles, "planes": B,
+                     "shape": eed4.SHAPE_NAMES[eed4.eed4_step_shape(B, wl.H, wl.W, p)]}
+    return res
+
+
 def batched_vs_single(eed4, torch, cycles):
     """64 uneven images (sides U{128..1024}, 2..8% masks, sigma 1.5, lambda 0.03,
     n 15): one eed4_inpaint_batched call (autotuned persistent kernels, graph)
@@ -347,6 +380,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-workloads", action="store_true")
     ap.add_argument("--batched-cycles", type=int, default=40)
     ap.add_argument("--adjoint-probe", action="store_true",
                     help="backward passes only (16 x 256x256 and one 4096x4096 cycle), for "
@@ -487,6 +521,9 @@ def main():
     if not args.no_variants:
         log("tensor variants (Table 7 diffusivities x mu3 choices)")
         out["variants"] = variants_timing(eed4, torch, u, mask, wl, stream)
+    if not args.no_workloads:
+        log("colour and scratch workloads (512x512)")
+        out["workloads"] = workload_throughput(eed4, torch)
     if not args.no_adjoint:
         log("adjoint / forward timing (16 x 256x256)")
         out["adjoint_forward_ratio"] = adjoint_ratio(eed4, torch, args)

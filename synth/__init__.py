@@ -16,6 +16,11 @@ from .generator import (
     make_problem,
     make_batch,
     make_uneven_batch,
+    make_rgb_problem,
+    make_scratch_mask,
+    make_scratch_problem,
+    make_workload_problem,
+    SCRATCH_WIDTH,
     WORKLOADS,
 )
 
@@ -26,5 +31,10 @@ __all__ = [
     "make_problem",
     "make_batch",
     "make_uneven_batch",
+    "make_rgb_problem",
+    "make_scratch_mask",
+    "make_scratch_problem",
+    "make_workload_problem",
+    "SCRATCH_WIDTH",
     "WORKLOADS",
 ]

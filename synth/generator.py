@@ -65,7 +65,24 @@ WORKLOADS = {
     "adjoint16": Workload("adjoint16", 256, 256, 30, True, 0.01, 0.04,
                           sigma=1.0, lam=0.05, tau=0.05, n=10, M=30, B=16,
                           seed_base=5000),
+    # colour: 512x512 RGB (3 channels sharing the ellipse geometry), one 5% mask
+    # for all channels, inpainted channel-wise as a batch of 3 planes
+    "rgb512": Workload("rgb512", 512, 512, 30, True, 0.01, 0.05,
+                       sigma=1.5, lam=0.03, tau=0.05, n=15, M=40, B=3,
+                       seed_base=6000),
+    # scratch removal: 512x512, scratches of width 2 covering 6% of the pixels
+    # (density = fraction of unknown pixels)
+    "scratch512_thin": Workload("scratch512_thin", 512, 512, 30, True, 0.01, 0.06,
+                                sigma=1.5, lam=0.03, tau=0.05, n=15, M=40,
+                                seed_base=7000),
+    # ... and scratches of width 6 covering 18%
+    "scratch512_thick": Workload("scratch512_thick", 512, 512, 30, True, 0.01, 0.18,
+                                 sigma=1.5, lam=0.03, tau=0.05, n=15, M=40,
+                                 seed_base=8000),
 }
+
+#: scratch width in pixels of the scratch workloads
+SCRATCH_WIDTH = {"scratch512_thin": 2, "scratch512_thick": 6}
 
 
 def make_image(H: int, W: int, n_ellipses: int, ramp: bool, noise_std: float,
@@ -170,3 +187,119 @@ def make_uneven_batch(wl: Workload, B: Optional[int] = None,
         p["density"] = dens
         out.append(p)
     return out
+
+
+def make_rgb_image(H: int, W: int, n_ellipses: int, ramp: bool, noise_std: float,
+                   rng: np.random.Generator) -> np.ndarray:
+    """Colour image [3, H, W] in FP64: the recipe of ``make_image`` with one
+    colour (three greys) per ellipse and for the background, so that edges
+    coincide across channels; the ramp has one direction and a random
+    amplitude per channel; the noise is independent per channel."""
+    img = np.empty((3, H, W), dtype=np.float64)
+    img[:] = rng.uniform(0.0, 1.0, size=3)[:, None, None]
+    m = float(min(H, W))
+    for _ in range(n_ellipses):
+        cy = rng.uniform(0.0, H)
+        cx = rng.uniform(0.0, W)
+        a = rng.uniform(0.05, 0.3) * m
+        b = rng.uniform(0.05, 0.3) * m
+        th = rng.uniform(0.0, np.pi)
+        colour = rng.uniform(0.0, 1.0, size=3)
+        rad = max(a, b)
+        y0, y1 = max(0, int(np.floor(cy - rad))), min(H, int(np.ceil(cy + rad)) + 1)
+        x0, x1 = max(0, int(np.floor(cx - rad))), min(W, int(np.ceil(cx + rad)) + 1)
+        if y0 >= y1 or x0 >= x1:
+            continue
+        yy = np.arange(y0, y1, dtype=np.float64)[:, None] - cy
+        xx = np.arange(x0, x1, dtype=np.float64)[None, :] - cx
+        c, s = np.cos(th), np.sin(th)
+        p = (xx * c + yy * s) / a
+        q = (-xx * s + yy * c) / b
+        inside = p * p + q * q <= 1.0
+        for ch in range(3):
+            img[ch, y0:y1, x0:x1][inside] = colour[ch]
+    if ramp:
+        phi = rng.uniform(0.0, 2.0 * np.pi)
+        amp = rng.uniform(0.15, 0.35, size=3)
+        yy = np.arange(H, dtype=np.float64)[:, None]
+        xx = np.arange(W, dtype=np.float64)[None, :]
+        r = xx * np.cos(phi) / W + yy * np.sin(phi) / H
+        lo, hi = r.min(), r.max()
+        r = (r - lo) / (hi - lo) if hi > lo else np.zeros_like(r)
+        for ch in range(3):
+            img[ch] = (1.0 - amp[ch]) * img[ch] + amp[ch] * r
+    if noise_std > 0:
+        img = img + rng.normal(0.0, noise_std, size=img.shape)
+    return np.clip(img, 0.0, 1.0)
+
+
+def make_rgb_problem(H: int, W: int, n_ellipses: int, ramp: bool, noise_std: float,
+                     density: float, seed: int) -> dict:
+    """Channel-wise colour inpainting problem: arrays [3, H, W]; one random mask
+    (exact count) shared by the three channels, replicated per channel."""
+    rng = np.random.default_rng(seed)
+    img = make_rgb_image(H, W, n_ellipses, ramp, noise_std, rng)
+    mask = make_mask(H, W, density, rng)
+    masks = np.repeat(mask[None], 3, 0)
+    known = np.where(masks != 0, img, 0.0)
+    u0 = np.stack([_initial_guess(img[c], mask) for c in range(3)])
+    return {
+        "image": img.astype(np.float32),
+        "mask": masks,
+        "known": known.astype(np.float32),
+        "u_init": u0.astype(np.float32),
+        "seed": seed,
+    }
+
+
+def make_scratch_mask(H: int, W: int, coverage: float, width: int,
+                      rng: np.random.Generator) -> np.ndarray:
+    """Scratch mask (uint8, 1 = known): straight scratches of the given width
+    are drawn one at a time (start uniform over the image, angle U[0, pi),
+    length U[0.2, 0.8] * min(H, W)) until they cover at least ``coverage`` of
+    the pixels; the scratched pixels are the unknown ones."""
+    unknown = np.zeros((H, W), dtype=bool)
+    target = coverage * H * W
+    yy = np.arange(H, dtype=np.float64)[:, None]
+    xx = np.arange(W, dtype=np.float64)[None, :]
+    half = 0.5 * width
+    while unknown.sum() < target:
+        y0 = rng.uniform(0.0, H)
+        x0 = rng.uniform(0.0, W)
+        th = rng.uniform(0.0, np.pi)
+        length = rng.uniform(0.2, 0.8) * min(H, W)
+        dy, dx = np.sin(th), np.cos(th)
+        # distance of every pixel centre to the segment
+        t = np.clip((yy - y0) * dy + (xx - x0) * dx, 0.0, length)
+        d2 = (yy - (y0 + t * dy)) ** 2 + (xx - (x0 + t * dx)) ** 2
+        unknown |= d2 <= half * half
+    return (~unknown).astype(np.uint8)
+
+
+def make_scratch_problem(H: int, W: int, n_ellipses: int, ramp: bool, noise_std: float,
+                         coverage: float, width: int, seed: int) -> dict:
+    """Scratch-removal problem: the image of ``make_problem`` with a scratch
+    mask (``coverage`` of the pixels unknown, scratches ``width`` wide)."""
+    rng = np.random.default_rng(seed)
+    img = make_image(H, W, n_ellipses, ramp, noise_std, rng)
+    mask = make_scratch_mask(H, W, coverage, width, rng)
+    known = np.where(mask != 0, img, 0.0)
+    u0 = _initial_guess(img, mask)
+    return {
+        "image": img.astype(np.float32),
+        "mask": mask,
+        "known": known.astype(np.float32),
+        "u_init": u0.astype(np.float32),
+        "seed": seed,
+    }
+
+
+def make_workload_problem(wl: Workload) -> dict:
+    """The problem of a colour or scratch workload (rgb512, scratch512_*)."""
+    if wl.name.startswith("rgb"):
+        return make_rgb_problem(wl.H, wl.W, wl.n_ellipses, wl.ramp, wl.noise_std,
+                                wl.density, wl.seed_base)
+    if wl.name in SCRATCH_WIDTH:
+        return make_scratch_problem(wl.H, wl.W, wl.n_ellipses, wl.ramp, wl.noise_std,
+                                    wl.density, SCRATCH_WIDTH[wl.name], wl.seed_base)
+    raise ValueError(f"{wl.name} is not a colour or scratch workload")

@@ -1,0 +1,96 @@
+"""Colour (channel-wise) and scratch-removal inpainting on the GPU against the
+FP64 oracle, through the C ABI.
+
+The paper inpaints RGB images channel-wise (Sec. 4.1) and removes thin (6 %)
+and thick (18 %) scratches (Sec. 4.2).  Here a colour image is an equal-size
+batch of three planes sharing one mask, and a scratch mask is a structured
+mask with most pixels known.  Bar: relative L2 <= 1e-5 per cycle from the
+oracle's state, RMSE <= 1e-4 at equal cycle counts.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth import WORKLOADS, make_rgb_problem, make_workload_problem
+from tests.helpers import REL_L2_PER_CYCLE, RMSE_STEADY, announce, rel_l2, rmse, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+import paper_2006_10406_amd as eed4  # noqa: E402
+
+
+def test_rgb_channelwise_run_and_single_channels():
+    wl = WORKLOADS["rgb512"]
+    H, W, M = 160, 200, 6
+    announce(f"rgb channel-wise {H}x{W}x3, {M} cycles of {wl.n}")
+    pr = make_rgb_problem(H, W, 12, True, 0.01, wl.density, 6100)
+    ref, cyc, rh = oracle.inpaint(pr["u_init"], pr["mask"], pr["known"], wl.lam, wl.sigma,
+                                  wl.tau, wl.n, M)
+    u = to_dev(pr["u_init"])
+    p = eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, M)
+    st, hist = eed4.eed4_inpaint(u, to_dev(pr["mask"]), to_dev(pr["known"]), p, history=True)
+    got = u.cpu().numpy()
+    errs = [rmse(got[c], ref[c]) for c in range(3)]
+    print(f"rgb {H}x{W}: RMSE vs FP64 per channel {', '.join(f'{e:.2e}' for e in errs)}; vs "
+          f"ground truth {rmse(got, pr['image']):.4f} (oracle {rmse(ref, pr['image']):.4f})")
+    assert st.cycles == cyc == M
+    assert max(errs) <= RMSE_STEADY
+    assert np.allclose(hist[:, :, 1], rh[:, :, 1], rtol=1e-5)
+    kn = pr["mask"] != 0
+    assert np.array_equal(got[kn], pr["known"][kn])
+    # channel-wise: each plane equals a single-channel run with the same kernel shape
+    shape = eed4.eed4_step_shape(3, H, W, p)
+    for c in range(3):
+        uc = to_dev(pr["u_init"][c])
+        pc = eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, M, flags=eed4.EED4_FORCE_SHAPE(shape))
+        eed4.eed4_inpaint(uc, to_dev(pr["mask"][c]), to_dev(pr["known"][c]), pc)
+        assert np.array_equal(uc.cpu().numpy(), got[c])
+
+
+def test_rgb512_per_cycle_parity():
+    wl = WORKLOADS["rgb512"]
+    M = 2
+    announce(f"rgb512 full size, per-cycle parity of {M} cycles")
+    pr = make_workload_problem(wl)
+    _, _, _, ck = oracle.inpaint(pr["u_init"], pr["mask"], pr["known"], wl.lam, wl.sigma, wl.tau,
+                                 wl.n, M, checkpoints=True)
+    states = ck.reshape(M * 3, wl.H, wl.W).astype(np.float32)
+    masks = np.tile(pr["mask"], (M, 1, 1))
+    knowns = np.tile(pr["known"], (M, 1, 1))
+    u = to_dev(states)
+    sums = torch.zeros((M * 3, 2), dtype=torch.float64, device="cuda")
+    eed4.eed4_fsi_cycle(u, to_dev(masks), to_dev(knowns), eed4.params(wl.lam, wl.sigma, wl.tau,
+                                                                      wl.n, 1), sums)
+    torch.cuda.synchronize()
+    got = u.cpu().numpy()
+    ref, _, _ = oracle.inpaint(states.astype(np.float64), masks, knowns, wl.lam, wl.sigma,
+                               wl.tau, wl.n, 1)
+    errs = [rel_l2(got[i], ref[i]) for i in range(M * 3)]
+    print(f"rgb512 per-cycle rel L2 vs FP64: max {max(errs):.3e}")
+    assert max(errs) <= REL_L2_PER_CYCLE
+
+
+@pytest.mark.parametrize("name", ["scratch512_thin", "scratch512_thick"])
+def test_scratch_removal_full_size(name):
+    wl = WORKLOADS[name]
+    M = 10
+    announce(f"{name}: {wl.H}x{wl.W}, {100 * wl.density:.0f}% scratched, {M} cycles of {wl.n}")
+    pr = make_workload_problem(wl)
+    ref, cyc, rh = oracle.inpaint(pr["u_init"], pr["mask"], pr["known"], wl.lam, wl.sigma,
+                                  wl.tau, wl.n, M)
+    u = to_dev(pr["u_init"])
+    st, hist = eed4.eed4_inpaint(u, to_dev(pr["mask"]), to_dev(pr["known"]),
+                                 eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, M), history=True)
+    got = u.cpu().numpy()
+    e = rmse(got, ref)
+    unk = pr["mask"] == 0
+    print(f"{name}: RMSE vs FP64 {e:.3e}; on the scratches vs ground truth "
+          f"{rmse(got[unk], pr['image'][unk]):.4f} (oracle {rmse(ref[unk], pr['image'][unk]):.4f}, "
+          f"initial {rmse(pr['u_init'][unk], pr['image'][unk]):.4f})")
+    assert st.cycles == cyc == M
+    assert e <= RMSE_STEADY
+    assert np.allclose(hist[:, 0, 1], rh[:, 1], rtol=1e-5)
+    assert np.array_equal(got[~unk], pr["known"][~unk])
