@@ -386,7 +386,10 @@ __device__ __forceinline__ void adjoint_strip_step(float *ring, const AdjStripAr
     const __amdgpu_buffer_rsrc_t rs_u = buffer_rsrc(s.u + base, (unsigned)nb * W4);
     const __amdgpu_buffer_rsrc_t rs_an = buffer_rsrc(s.an + base, (unsigned)nb * W4);
     const __amdgpu_buffer_rsrc_t rs_ac = buffer_rsrc(s.ac + base, (unsigned)nb * W4);
-    const __amdgpu_buffer_rsrc_t rs_ap = buffer_rsrc(s.ap + base, (unsigned)nb * W4);
+    // at k = 0 the (1 - alpha) r term stays in ubar^k: the ubar^{k-1} resource
+    // then has no records, so its stores are dropped
+    const __amdgpu_buffer_rsrc_t rs_ap = buffer_rsrc(s.ap + base, s.first ? 0u : (unsigned)nb * W4);
+    const float keep_back = s.first ? 1.0f : 0.0f;
     const __amdgpu_buffer_rsrc_t rs_m = buffer_rsrc(s.mask + base, (unsigned)nb * (unsigned)W);
 
     const int c0 = s.X0 - G::hc;                              // column of lane 0
@@ -546,8 +549,8 @@ __device__ __forceinline__ void adjoint_strip_step(float *ring, const AdjStripAr
                 float acv = fmaf(s.alpha, fmaf(-s.tau, pro + cq, rv), cur.oc);
                 const float back = (1.0f - s.alpha) * rv;
                 const unsigned ro = (unsigned)(o - b0) * W4;
-                if (s.first) acv += back;
-                else __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(back), rs_ap, vo4, ro, 0);
+                acv = fmaf(keep_back, back, acv);
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(back), rs_ap, vo4, ro, 0);
                 if (mk) acv += anv;                                  // known pixel: running sum
                 __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acv), rs_ac, vo4, ro, 0);
             }

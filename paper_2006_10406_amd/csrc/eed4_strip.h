@@ -126,8 +126,13 @@ __device__ __forceinline__ void model_mu(float x, int model, float &mu1, float &
 // and a store there is dropped: lanes without an output pixel use kOffNone.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, unsigned bytes)
 {
+    // The empty asm makes the size and flag words opaque, so resources with
+    // equal words get SGPRs of their own: otherwise the compiler keeps one copy
+    // and rebuilds the four-register descriptor before every access in the loop.
+    int flags = 0x00020000;
+    asm volatile("" : "+s"(bytes), "+s"(flags));
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
-                                             0x00020000);
+                                             flags);
 }
 constexpr unsigned kOffNone = 0x80000000u;
 
