@@ -44,14 +44,71 @@ constexpr int kAdjTW = 64, kAdjTH = 16;
 // e = A : D(G) : H.  In the gradient frame n = G/|G|, t = n rotated by +90
 // degrees, e = A:H + (mu1 - 1) a1 h1 + 2 (mu3 - 1) a3 h3 with a1 = n.A.n,
 // a3 = t.A.n; d/ds and d/dtheta of it give q = (de/ds) n + (1/s)(de/dtheta) t.
+// Eigenvalue data of a tensor variant (diffusivities of Table 7, mu3 choices
+// of Sec. 3.1) at x = (s/lambda)^2: mu1 = g(x), mu3, their derivatives G1, G3
+// with respect to x, and Q1 = (mu1 - 1)/x, Q3 = (mu3 - 1)/x, written so that
+// they stay finite at x = 0 (every variant has g(0) = 1).
+struct MuData {
+    float mu1, mu3, G1, G3, Q1, Q3;
+};
+
+__device__ __forceinline__ MuData model_mu_data(float x, int model)
+{
+    const int diff = model & 0xf, rule = model >> 4;
+    const float d = 1.0f + x;
+    MuData m;
+    if (diff == kDiffPeronaMalik) {                  // (1 + x)^-1
+        m.mu1 = __builtin_amdgcn_rcpf(d);
+        m.G1 = -m.mu1 * m.mu1;
+        m.Q1 = -m.mu1;
+    } else if (diff == kDiffPeronaMalikExp) {        // exp(-x)
+        m.mu1 = expf(-x);
+        m.G1 = -m.mu1;
+        m.Q1 = x > 0.0f ? expm1f(-x) / x : -1.0f;
+    } else if (diff == kDiffGemanReynolds) {         // (1 + x)^-2
+        const float r = __builtin_amdgcn_rcpf(d);
+        m.mu1 = r * r;
+        m.G1 = -2.0f * m.mu1 * r;
+        m.Q1 = -(2.0f + x) * m.mu1;
+    } else {                                         // Charbonnier (1 + x)^-1/2
+        m.mu1 = __builtin_amdgcn_rsqf(d);
+        m.G1 = -0.5f * m.mu1 * m.mu1 * m.mu1;
+        m.Q1 = -m.mu1 * m.mu1 * __builtin_amdgcn_rcpf(1.0f + m.mu1);
+    }
+    if (rule == kMu3Arithmetic) {                    // (mu1 + mu2)/2
+        m.mu3 = 0.5f * (1.0f + m.mu1);
+        m.G3 = 0.5f * m.G1;
+        m.Q3 = 0.5f * m.Q1;
+    } else if (rule == kMu3Max) {                    // max(mu1, mu2) = 1
+        m.mu3 = 1.0f;
+        m.G3 = 0.0f;
+        m.Q3 = 0.0f;
+    } else {                                         // sqrt(mu1 mu2)
+        m.mu3 = __builtin_amdgcn_sqrtf(m.mu1);
+        m.G3 = m.mu1 > 0.0f ? 0.5f * m.G1 * __builtin_amdgcn_rcpf(m.mu3) : 0.0f;
+        m.Q3 = m.Q1 * __builtin_amdgcn_rcpf(1.0f + m.mu3);
+    }
+    return m;
+}
+
+template <bool GEN = false>
 __device__ __forceinline__ void adjoint_point(float gx, float gy, float inv_lam2, float inv_lam3,
                                               float axx, float ayy, float axy, float hxx,
                                               float hyy, float hxy, float &txx, float &tyy,
-                                              float &txy, float &qx, float &qy, float &dl)
+                                              float &txy, float &qx, float &qy, float &dl,
+                                              int model = 0)
 {
     const float s2 = fmaf(gx, gx, gy * gy);
-    const float mu1 = __builtin_amdgcn_rsqf(fmaf(s2, inv_lam2, 1.0f));
-    const float mu3 = __builtin_amdgcn_sqrtf(mu1);
+    float mu1, mu3;
+    MuData md{};
+    if constexpr (GEN) {
+        md = model_mu_data(s2 * inv_lam2, model);
+        mu1 = md.mu1;
+        mu3 = md.mu3;
+    } else {
+        mu1 = __builtin_amdgcn_rsqf(fmaf(s2, inv_lam2, 1.0f));
+        mu3 = __builtin_amdgcn_sqrtf(mu1);
+    }
     const float rn = __builtin_amdgcn_rsqf(fmaxf(s2, 1e-30f));
     const float s = s2 * rn;                   // |G| (0 when G = 0)
     const float nx = gx * rn, ny = gy * rn;
@@ -70,16 +127,28 @@ __device__ __forceinline__ void adjoint_point(float gx, float gy, float inv_lam2
     txx = fmaf(k1, a, axx - k3c2);
     tyy = fmaf(k1, b, ayy + k3c2);
     txy = fmaf(k1, c, fmaf(k3, amb, axy));
-    // derivatives: dmu1/ds = -s mu1^3 / lam^2, dmu3/ds = -s mu1^(5/2) / (2 lam^2)
-    const float m12 = mu1 * mu1;
-    const float X = fmaf(m12 * mu1, a1 * h1, m12 * mu3 * (a3 * h3));
-    const float de_ds = -s * inv_lam2 * X;
-    dl = (s2 * inv_lam3) * X;
-    // (mu1 - 1)/s = -s mu1^2 / (lam^2 (1 + mu1)), (mu3 - 1)/s = that / (1 + mu3)
-    const float rp = __builtin_amdgcn_rcpf((1.0f + mu1) * (1.0f + mu3));
-    const float p1 = fmaf(a3, h1, a1 * h3);
-    const float p2 = fmaf(at - a1, h3, a3 * (ht - h1));
-    const float dth = -2.0f * s * m12 * inv_lam2 * rp * fmaf(p1, 1.0f + mu3, p2);
+    float de_ds, dth;
+    if constexpr (GEN) {
+        // with x = s^2/lambda^2: d mu/ds = 2 s/lambda^2 dmu/dx, d mu/dlambda =
+        // -2 s^2/lambda^3 dmu/dx, and (mu - 1)/s = s/lambda^2 (mu - 1)/x
+        const float Y = fmaf(md.G1, a1 * h1, 2.0f * md.G3 * (a3 * h3));
+        de_ds = 2.0f * s * inv_lam2 * Y;
+        dl = -2.0f * (s2 * inv_lam3) * Y;
+        const float p1 = fmaf(a3, h1, a1 * h3);
+        const float p2 = fmaf(at - a1, h3, a3 * (ht - h1));
+        dth = 2.0f * s * inv_lam2 * fmaf(md.Q1, p1, md.Q3 * p2);
+    } else {
+        // derivatives: dmu1/ds = -s mu1^3 / lam^2, dmu3/ds = -s mu1^(5/2) / (2 lam^2)
+        const float m12 = mu1 * mu1;
+        const float X = fmaf(m12 * mu1, a1 * h1, m12 * mu3 * (a3 * h3));
+        de_ds = -s * inv_lam2 * X;
+        dl = (s2 * inv_lam3) * X;
+        // (mu1 - 1)/s = -s mu1^2 / (lam^2 (1 + mu1)), (mu3 - 1)/s = that / (1 + mu3)
+        const float rp = __builtin_amdgcn_rcpf((1.0f + mu1) * (1.0f + mu3));
+        const float p1 = fmaf(a3, h1, a1 * h3);
+        const float p2 = fmaf(at - a1, h3, a3 * (ht - h1));
+        dth = -2.0f * s * m12 * inv_lam2 * rp * fmaf(p1, 1.0f + mu3, p2);
+    }
     qx = fmaf(nx, de_ds, -ny * dth);
     qy = fmaf(ny, de_ds, nx * dth);
 }
@@ -357,6 +426,7 @@ struct AdjStripArgs {
     int H, W, X0, Y0;
     float tau, alpha, il2, il3; // il2 = 1/lambda^2, il3 = 1/lambda^3
     int first;                  // k == 0: the (1-alpha) r term goes to ubar^k itself
+    int model;                  // tensor variant (GEN kernels only)
 };
 
 // Global loads of one stream row: u^k of the row, r of the row R above it,
@@ -366,7 +436,7 @@ struct AdjStripRow {
     unsigned rmk, omk;
 };
 
-template <int R, int ROWS>
+template <int R, int ROWS, bool GEN = false>
 __device__ __forceinline__ void adjoint_strip_step(float *ring, const AdjStripArgs &s,
                                                    const float (&w)[2 * kRMax + 1],
                                                    double *partial, float lam_scale)
@@ -507,8 +577,8 @@ __device__ __forceinline__ void adjoint_strip_step(float *ring, const AdjStripAr
             r_m1 = r_0;
             r_0 = r_p1;
             float tx, ty, txy, qx, qy, dl;
-            adjoint_point(0.5f * gxs, 0.5f * gys, s.il2, s.il3, axx, ayy, axy, hxx, hyy, hxy, tx,
-                          ty, txy, qx, qy, dl);
+            adjoint_point<GEN>(0.5f * gxs, 0.5f * gys, s.il2, s.il3, axx, ayy, axy, hxx, hyy, hxy,
+                               tx, ty, txy, qx, qy, dl, s.model);
             const int g = ybase + i - R - 1;                          // image row of S3
             dsum += (g >= s.Y0 && g < yend && out_lane) ? (double)dl : 0.0;
             const float z = from_next_lane(txy) - from_prev_lane(txy);
@@ -563,14 +633,13 @@ __device__ __forceinline__ void adjoint_strip_step(float *ring, const AdjStripAr
     partial[0] = prev + (double)lam_scale * tot;
 }
 
-template <int R, int ROWS>
-__global__ __launch_bounds__(256) void adjoint_strip_kernel(const float *u_all, const float *an_all,
-                                                            float *ac_all, float *ap_all,
-                                                            const uint8_t *__restrict__ mask_all,
-                                                            int H, int W, int nstrip, int per_img,
-                                                            int nitems, StepArgs a, float il3,
-                                                            float lam_scale, int first,
-                                                            double *lam_partials)
+template <int R, int ROWS, bool GEN>
+__device__ __forceinline__ void adjoint_strip_body(const float *u_all, const float *an_all,
+                                                   float *ac_all, float *ap_all,
+                                                   const uint8_t *__restrict__ mask_all, int H,
+                                                   int W, int nstrip, int per_img, int nitems,
+                                                   const StepArgs &a, float il3, float lam_scale,
+                                                   int first, double *lam_partials)
 {
     using G = AdjStripGeo<R, ROWS>;
     __shared__ float lds[4 * G::LDS];
@@ -596,8 +665,34 @@ __global__ __launch_bounds__(256) void adjoint_strip_kernel(const float *u_all, 
     s.il2 = a.inv_lam2;
     s.il3 = il3;
     s.first = first;
-    adjoint_strip_step<R, ROWS>(lds + wave * G::LDS, s, a.w, lam_partials + 2 * (size_t)item,
-                                lam_scale);
+    s.model = a.model;
+    adjoint_strip_step<R, ROWS, GEN>(lds + wave * G::LDS, s, a.w,
+                                     lam_partials + 2 * (size_t)item, lam_scale);
+}
+
+template <int R, int ROWS>
+__global__ __launch_bounds__(256) void adjoint_strip_kernel(const float *u_all, const float *an_all,
+                                                            float *ac_all, float *ap_all,
+                                                            const uint8_t *__restrict__ mask_all,
+                                                            int H, int W, int nstrip, int per_img,
+                                                            int nitems, StepArgs a, float il3,
+                                                            float lam_scale, int first,
+                                                            double *lam_partials)
+{
+    adjoint_strip_body<R, ROWS, false>(u_all, an_all, ac_all, ap_all, mask_all, H, W, nstrip,
+                                       per_img, nitems, a, il3, lam_scale, first, lam_partials);
+}
+
+// The reverse step of the tensor variants (diffusivities of Table 7, mu3
+// choices of Sec. 3.1) on strips of >= 28 rows.
+template <int R>
+__global__ __launch_bounds__(256) void adjoint_strip_model_kernel(
+    const float *u_all, const float *an_all, float *ac_all, float *ap_all,
+    const uint8_t *__restrict__ mask_all, int H, int W, int nstrip, int per_img, int nitems,
+    StepArgs a, float il3, float lam_scale, int first, double *lam_partials)
+{
+    adjoint_strip_body<R, 28, true>(u_all, an_all, ac_all, ap_all, mask_all, H, W, nstrip,
+                                    per_img, nitems, a, il3, lam_scale, first, lam_partials);
 }
 
 // ---- small helper kernels ----
@@ -753,9 +848,29 @@ static hipError_t launch_rev_strip(const RevStep &t, const StepArgs &a, float il
 }
 
 template <int R>
+static hipError_t launch_rev_model(const RevStep &t, const StepArgs &a, float il3, float ls,
+                                   hipStream_t s)
+{
+    using G = AdjStripGeo<R, 28>;
+    const int nstrip = (t.W + G::SW - 1) / G::SW;
+    const int per_img = adj_strip_items_t<R, 28>(t.H, t.W);
+    const long long nitems = (long long)per_img * t.B;
+    if (nitems > (1LL << 31) - 4) return hipErrorInvalidValue;
+    const unsigned nblk = (unsigned)((nitems + 3) / 4);
+    hipLaunchKernelGGL((adjoint_strip_model_kernel<R>), dim3(nblk), dim3(256), 0, s, t.u, t.an,
+                       t.ac, t.ap, t.mask, t.H, t.W, nstrip, per_img, (int)nitems, a, il3, ls,
+                       t.first, t.lp);
+    return hipGetLastError();
+}
+
+template <int R>
 static hipError_t launch_rev_r(const RevStep &t, const StepArgs &a, float il3, float ls,
                                hipStream_t s)
 {
+    // tensor variants: one kernel shape (strips of >= 28 rows)
+    if (a.model != 0)
+        return t.shape == kShapeStripShort ? launch_rev_model<R>(t, a, il3, ls, s)
+                                           : hipErrorInvalidValue;
     switch (t.shape) {
     case kShapeStrip:
     case kShapeStripWide: return launch_rev_strip<R, 64>(t, a, il3, ls, s);
@@ -771,7 +886,7 @@ static hipError_t launch_rev_r(const RevStep &t, const StepArgs &a, float il3, f
 static hipError_t launch_reverse_step(const RevStep &t, const eed4_params *p, int k,
                                       hipStream_t s)
 {
-    const StepArgs a = make_args(p->sigma, t.R, p->tau, p->lambda, k);
+    const StepArgs a = make_args(p->sigma, t.R, p->tau, p->lambda, k, model_of_flags(p->flags));
     const float il3 = (float)(1.0 / ((double)p->lambda * p->lambda * p->lambda));
     const float ls = -a.alpha * a.tau;
     const int R = t.R;
@@ -860,6 +975,7 @@ static std::string adjoint_tune_key(int R, int B, int H, int W)
 // on the caller's data (t holds real buffers; what it writes is scratch).
 static int adjoint_shape(const eed4_params *p, RevStep t, hipStream_t s, int *shape)
 {
+    if (model_of_flags(p->flags) != 0) { *shape = kShapeStripShort; return EED4_OK; }
     const int forced = (p->flags >> 8) & 0xff;
     if (forced >= 1 && forced <= kNumShapes) { *shape = forced - 1; return EED4_OK; }
     if (p->flags & EED4_TILE_KERNEL) { *shape = 0; return EED4_OK; }
@@ -897,7 +1013,6 @@ extern "C" int eed4_backward(const float *ckpt, const uint8_t *mask, const float
 {
     int rc = check_params(p, B, H, W);
     if (rc != EED4_OK) return rc;
-    if (model_of_flags(p->flags) != 0) return EED4_EINVAL;   // adjoint of the FOEED tensor only
     if (!ckpt || !mask || !known || !grad_u || !grad_known || !grad_init || !grad_lambda || M < 1)
         return EED4_EINVAL;
     const int n = p->cycle_len, R = eed4_radius(p->sigma);
@@ -964,7 +1079,7 @@ extern "C" int eed4_backward(const float *ckpt, const uint8_t *mask, const float
         U[0] = ckpt + (size_t)m * N;
         for (int k = 0; k + 1 < n; ++k) {
             float *out = Uset[m & 1] + (size_t)k * N;
-            StepArgs a = make_args(p->sigma, R, p->tau, p->lambda, k);
+            StepArgs a = make_args(p->sigma, R, p->tau, p->lambda, k, model_of_flags(p->flags));
             hipError_t r = launch_step(R, fshape, U[k], U[k > 0 ? k - 1 : 0], out, nullptr, mask,
                                        B, H, W, a, nullptr, s1);
             if (r != hipSuccess) return r;

@@ -318,8 +318,7 @@ size_t eed4_workspace_size(int op, int B, int H, int W, const eed4_params *p)
     if (((p->flags >> 8) & 0xff) > kNumShapes) return 0;
     if (op == EED4_OP_INPAINT || op == EED4_OP_CYCLE)
         return inpaint_layout(op, B, H, W, eed4_radius(p->sigma), p->max_cycles).total;
-    if (op == EED4_OP_BACKWARD)
-        return model_of_flags(p->flags) != 0 ? 0 : backward_workspace(B, H, W, p);
+    if (op == EED4_OP_BACKWARD) return backward_workspace(B, H, W, p);
     return 0;
 }
 

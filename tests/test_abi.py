@@ -106,8 +106,8 @@ def test_step_shape_query_without_tuning(lib):
 
 
 def test_tensor_variant_flags(lib):
-    # the variants of Table 7 / Sec. 3.1 run the 28-row strip kernel; bad fields, other
-    # shapes, the adjoint and the batched path are rejected before any device work
+    # the variants of Table 7 / Sec. 3.1 run the 28-row strip kernels; bad fields, other
+    # shapes and the batched path are rejected before any device work
     import ctypes
     import paper_2006_10406_amd as e
     q = lambda p, B=1, H=300, W=200: lib.eed4_step_shape(B, H, W, ctypes.byref(p))
@@ -121,7 +121,7 @@ def test_tensor_variant_flags(lib):
             if fl:
                 assert q(p, 1, 40, 30) == 5
                 assert e.eed4_workspace_size(e.EED4_OP_INPAINT, 1, 64, 64, p) > 0
-                assert e.eed4_workspace_size(e.EED4_OP_BACKWARD, 1, 64, 64, p) == 0
+                assert e.eed4_workspace_size(e.EED4_OP_BACKWARD, 1, 64, 64, p) > 0
     var = e.EED4_DIFFUSIVITY(e.EED4_PERONA_MALIK_EXP) | e.EED4_MU3(e.EED4_MU3_ARITHMETIC)
     assert q(e.params(0.05, 1.0, 0.05, 10, 2, flags=var | e.EED4_FORCE_SHAPE(5))) == 5
     assert q(e.params(0.05, 1.0, 0.05, 10, 2, flags=var | e.EED4_FORCE_SHAPE(3))) == EINVAL
@@ -131,7 +131,8 @@ def test_tensor_variant_flags(lib):
     assert _call_inpaint(lib, e.params(0.05, 1.0, 0.05, 10, 2, flags=e.EED4_MU3(3))) == EINVAL
     pv = e.params(0.05, 1.0, 0.05, 10, 2, flags=var)
     fake = 0x2000
-    assert lib.eed4_backward(fake, fake, fake, 1, 8, 8, ctypes.byref(pv), 2, fake, fake, fake,
+    bad = e.params(0.05, 1.0, 0.05, 10, 2, flags=var | e.EED4_FORCE_SHAPE(3))
+    assert lib.eed4_backward(fake, fake, fake, 1, 8, 8, ctypes.byref(bad), 2, fake, fake, fake,
                              fake, 0x1000, 1 << 40, None) == EINVAL
     img = e._lib.eed4_image(fake, fake, fake, 8, 8, 0.05)
     assert lib.eed4_inpaint_batched(ctypes.byref(img), 1, ctypes.byref(pv), 0x1000, 1 << 40,

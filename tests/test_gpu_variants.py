@@ -104,3 +104,41 @@ def test_variant_differs_from_foeed():
                           eed4.params(0.05, 1.0, 0.05, 10, 3, flags=fl))
         outs.append(u.cpu().numpy())
     assert rel_l2(outs[0], outs[1]) > 1e-4
+
+
+# ------------------------------------------------------------ adjoint of the variants
+ADJ_TOL = 1e-4
+
+
+def variant_forward_backward(b, lam, sigma, tau, n, M, gu, flags):
+    u = to_dev(b["u_init"])
+    mask, known = to_dev(b["mask"]), to_dev(b["known"])
+    B, H, W = u.shape
+    p = eed4.params(lam, sigma, tau, n, M, flags=flags)
+    ck = torch.empty((M, B, H, W), dtype=torch.float32, device="cuda")
+    eed4.eed4_inpaint(u, mask, known, p, ckpt=ck)
+    g = to_dev(gu.astype(np.float32))
+    gk, gi = torch.empty_like(g), torch.empty_like(g)
+    gl = torch.empty(B, device="cuda")
+    eed4.eed4_backward(ck, mask, known, p, M, g, gk, gi, gl)
+    torch.cuda.synchronize()
+    return ck.cpu().numpy(), gk.cpu().numpy(), gi.cpu().numpy(), gl.cpu().numpy()
+
+
+@pytest.mark.parametrize("d,r", [c for c in COMBOS if c != (0, 0)])
+@pytest.mark.parametrize("H,W,sigma,lam,n,M", [(56, 90, 1.0, 0.05, 4, 2), (97, 70, 2.0, 0.03, 3, 2)])
+def test_adjoint_matches_oracle(d, r, H, W, sigma, lam, n, M):
+    # eed4_backward of a variant against the FP64 oracle's adjoint of the same variant, on the
+    # trajectory the GPU forward checkpointed
+    announce(f"variant adjoint {label(d, r)} {H}x{W} sigma={sigma} n={n} M={M}")
+    b = {k: np.stack([make_problem(H, W, 5, True, 0.01, 0.07, 950 + i + 7 * d + r)[k]
+                      for i in range(2)]) for k in ("image", "mask", "known", "u_init")}
+    gu = np.random.default_rng(H + 13 * d + r).normal(size=b["u_init"].shape) * 1e-2
+    ck, gk, gi, gl = variant_forward_backward(b, lam, sigma, 0.05, n, M, gu, flags_of(d, r))
+    ogk, ogi, ogl = oracle.backward(ck.astype(np.float64), b["mask"], b["known"], lam, sigma,
+                                    0.05, n, gu, diff=d, mu3=r)
+    m = b["mask"] != 0
+    ek, ei, el = rel_l2(gk[m], ogk[m]), rel_l2(gi[~m], ogi[~m]), rel_l2(gl, ogl)
+    print(f"{label(d, r)} {H}x{W}: rel L2 dL/df {ek:.2e}, dL/du_init {ei:.2e}, dL/dlambda {el:.2e}")
+    assert np.all(gk[~m] == 0) and np.all(gi[m] == 0)
+    assert ek <= ADJ_TOL and ei <= ADJ_TOL and el <= ADJ_TOL
