@@ -21,13 +21,15 @@ class EED4Inpaint(torch.autograd.Function):
     """u = inpaint(known, lam, u_init; mask) over M fixed FSI cycles.
 
     known, u_init: float32 [B,H,W] on the GPU; mask: uint8 [B,H,W];
-    lam: 0-dim float tensor (one contrast for the batch).
+    lam: 0-dim float tensor (one contrast for the batch); flags: EED4_* flags
+    (e.g. a tensor variant, EED4_DIFFUSIVITY(d) | EED4_MU3(r)).
     Gradients: d/dknown (on the mask), d/dlam (summed over the batch),
     d/du_init (off the mask)."""
 
     @staticmethod
-    def forward(ctx, known, lam, u_init, mask, sigma: float, tau: float, n: int, M: int):
-        p = params(float(lam), sigma, tau, n, M)
+    def forward(ctx, known, lam, u_init, mask, sigma: float, tau: float, n: int, M: int,
+                flags: int = 0):
+        p = params(float(lam), sigma, tau, n, M, flags=flags)
         u = u_init.detach().clone().contiguous()
         known_c = known.detach().contiguous()
         ck = torch.empty((M,) + tuple(u.shape), dtype=torch.float32, device=u.device)
@@ -47,7 +49,7 @@ class EED4Inpaint(torch.autograd.Function):
         B = g.shape[0] if g.dim() == 3 else 1
         gl = torch.empty(B, dtype=torch.float32, device=g.device)
         eed4_backward(ck, mask, known, ctx.p, ctx.M, g, gk, gi, gl)
-        return gk, gl.sum().reshape(ctx.lam_shape), gi, None, None, None, None, None
+        return gk, gl.sum().reshape(ctx.lam_shape), gi, None, None, None, None, None, None
 
 
 def mean_fill(known: torch.Tensor, mask: torch.Tensor) -> torch.Tensor:
@@ -58,18 +60,19 @@ def mean_fill(known: torch.Tensor, mask: torch.Tensor) -> torch.Tensor:
     return m * known + (1.0 - m) * mean
 
 
-def inpaint(known, lam, mask, sigma, tau, n, M, u_init: Optional[torch.Tensor] = None):
+def inpaint(known, lam, mask, sigma, tau, n, M, u_init: Optional[torch.Tensor] = None,
+            flags: int = 0):
     """Differentiable inpainting; u_init defaults to the mean fill of known."""
     if u_init is None:
         u_init = mean_fill(known, mask)
     if not torch.is_tensor(lam):
         lam = torch.tensor(float(lam), device=known.device)
-    return EED4Inpaint.apply(known, lam, u_init, mask, sigma, tau, n, M)
+    return EED4Inpaint.apply(known, lam, u_init, mask, sigma, tau, n, M, flags)
 
 
 def tonal_optimize(image: torch.Tensor, mask: torch.Tensor, lam: float, sigma: float,
                    tau: float, n: int, M: int, steps: int = 50, lr: float = 5e-3,
-                   optimize_lambda: bool = False) -> dict:
+                   optimize_lambda: bool = False, flags: int = 0) -> dict:
     """Adam on the known values (and optionally lambda) to minimise the MSE of
     the reconstruction against the original image.  Returns the loss history
     and the optimised tensors."""
@@ -81,13 +84,13 @@ def tonal_optimize(image: torch.Tensor, mask: torch.Tensor, lam: float, sigma: f
     hist: List[float] = []
     for _ in range(steps):
         opt.zero_grad(set_to_none=True)
-        u = inpaint(known, lam_t, mask, sigma, tau, n, M)
+        u = inpaint(known, lam_t, mask, sigma, tau, n, M, flags=flags)
         loss = torch.mean((u - image) ** 2)
         loss.backward()
         known.grad.mul_(m)          # only stored pixels are free
         opt.step()
         hist.append(float(loss.detach()))
     with torch.no_grad():
-        u = inpaint(known, lam_t, mask, sigma, tau, n, M)
+        u = inpaint(known, lam_t, mask, sigma, tau, n, M, flags=flags)
         final = float(torch.mean((u - image) ** 2))
     return {"loss": hist, "final_loss": final, "known": known.detach(), "lam": float(lam_t)}

@@ -142,3 +142,37 @@ def test_adjoint_matches_oracle(d, r, H, W, sigma, lam, n, M):
     print(f"{label(d, r)} {H}x{W}: rel L2 dL/df {ek:.2e}, dL/du_init {ei:.2e}, dL/dlambda {el:.2e}")
     assert np.all(gk[~m] == 0) and np.all(gi[m] == 0)
     assert ek <= ADJ_TOL and ei <= ADJ_TOL and el <= ADJ_TOL
+
+
+def test_autograd_with_a_variant():
+    # the torch.autograd wrapper passes the variant to both directions: its gradient equals a
+    # direct eed4_backward call, and tonal optimisation lowers the MSE
+    from paper_2006_10406_amd import autograd as ea
+    d, r = 1, 1
+    H, W, lam, sigma, tau, n, M = 64, 80, 0.04, 1.0, 0.05, 5, 3
+    announce(f"autograd with variant {label(d, r)}, {H}x{W}")
+    fl = flags_of(d, r)
+    b = {k: np.stack([make_problem(H, W, 6, True, 0.01, 0.06, 990 + i)[k] for i in range(2)])
+         for k in ("image", "mask", "known", "u_init")}
+    image, mask = to_dev(b["image"]), to_dev(b["mask"])
+    known = torch.nn.Parameter(to_dev(b["known"]))
+    u0 = ea.mean_fill(known.detach(), mask)
+    u = ea.inpaint(known, torch.tensor(lam, device="cuda"), mask, sigma, tau, n, M, u_init=u0,
+                   flags=fl)
+    loss = torch.sum((u - image) ** 2)
+    loss.backward()
+    # direct: forward with checkpoints, then eed4_backward of the same loss
+    p = eed4.params(lam, sigma, tau, n, M, flags=fl)
+    ud = u0.clone()
+    ck = torch.empty((M, 2, H, W), dtype=torch.float32, device="cuda")
+    eed4.eed4_inpaint(ud, mask, known.detach().contiguous(), p, ckpt=ck)
+    assert torch.equal(ud, u.detach())
+    g = (2.0 * (ud - image)).contiguous()
+    gk, gi = torch.empty_like(g), torch.empty_like(g)
+    gl = torch.empty(2, device="cuda")
+    eed4.eed4_backward(ck, mask, known.detach().contiguous(), p, M, g, gk, gi, gl)
+    torch.cuda.synchronize()
+    assert torch.equal(known.grad, gk)
+    out = ea.tonal_optimize(image, mask, lam, sigma, tau, n, M, steps=8, lr=5e-3, flags=fl)
+    print(f"{label(d, r)} tonal optimisation MSE {out['loss'][0]:.6f} -> {out['final_loss']:.6f}")
+    assert out["final_loss"] < out["loss"][0]
