@@ -294,14 +294,52 @@ def test_long_thin_images_one_cycle(shape, H, W):
 
 
 def test_large4096_first_cycle_parity():
+    # full size, in the kernel shapes the benchmark runs: the autotuner's usual choices
+    # (28- and 64-row strips) and the shape eed4_inpaint picks in this process
     wl = WORKLOADS["large4096"]
     announce("large4096 first cycle (bench launch configuration) vs oracle")
     pr = make_problem(wl.H, wl.W, wl.n_ellipses, wl.ramp, wl.noise_std, wl.density, wl.seed_base)
     u0 = np.where(pr["mask"] != 0, pr["known"], pr["u_init"]).astype(np.float32)
-    got, sums = gpu_cycle(u0[None], pr["mask"][None], pr["known"][None], wl.lam, wl.sigma,
-                          wl.tau, wl.n)
     ref, rh = oracle_cycle(u0[None], pr["mask"][None], pr["known"][None], wl.lam, wl.sigma,
                            wl.tau, wl.n)
-    e = rel_l2(got[0], ref[0])
-    print(f"large4096 first cycle rel L2 {e:.3e}, max abs {np.abs(got[0] - ref[0]).max():.3e}")
+    u = to_dev(u0)
+    eed4.eed4_inpaint(u, to_dev(pr["mask"]), to_dev(pr["known"]),
+                      eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, 1))
+    tuned = eed4.eed4_step_shape(1, wl.H, wl.W, eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, 1))
+    got_tuned = u.cpu().numpy()
+    e = rel_l2(got_tuned, ref[0])
+    print(f"large4096 first cycle, autotuned {eed4.SHAPE_NAMES[tuned]}: rel L2 {e:.3e}, "
+          f"max abs {np.abs(got_tuned - ref[0]).max():.3e}")
     assert e <= REL_L2_PER_CYCLE
+    for shape in (3, 5):
+        got, sums = gpu_cycle(u0[None], pr["mask"][None], pr["known"][None], wl.lam, wl.sigma,
+                              wl.tau, wl.n, flags=eed4.EED4_FORCE_SHAPE(shape))
+        e = rel_l2(got[0], ref[0])
+        print(f"large4096 first cycle {eed4.SHAPE_NAMES[shape]}: rel L2 {e:.3e}")
+        assert e <= REL_L2_PER_CYCLE
+        assert np.allclose(np.sqrt(sums[0, 1]), rh[0, 0, 1], rtol=1e-6)
+        if shape == tuned:
+            assert np.array_equal(got[0], got_tuned)
+
+
+def test_empty_mask_smoothing_case():
+    # no known pixels: the evolution is the smoothing variant (Sec. 3.3); mean grey value is
+    # preserved (P 1 = 0 and P symmetric) and the cycle matches the oracle
+    announce("empty mask (smoothing), 90x130, 2 cycles")
+    pr = make_problem(90, 130, 6, True, 0.01, 0.05, 4242)
+    mask = np.zeros((90, 130), np.uint8)
+    st = pr["image"][None].astype(np.float32)
+    got, _ = gpu_cycle(st, mask[None], st, 0.05, 1.0, 0.05, 10)
+    ref, _ = oracle_cycle(st, mask[None], st, 0.05, 1.0, 0.05, 10)
+    assert rel_l2(got, ref) <= REL_L2_PER_CYCLE
+    assert abs(float(got.astype(np.float64).mean()) - float(st.astype(np.float64).mean())) < 1e-6
+
+
+def test_all_known_mask_is_held():
+    announce("all-known mask, 50x70")
+    pr = make_problem(50, 70, 4, True, 0.01, 0.05, 4343)
+    mask = np.ones((50, 70), np.uint8)
+    u = to_dev(np.full((50, 70), 0.5, np.float32))
+    st = eed4.eed4_inpaint(u, to_dev(mask), to_dev(pr["image"]), eed4.params(0.05, 1.0, 0.05, 10, 3))[0]
+    assert np.array_equal(u.cpu().numpy(), pr["image"])
+    assert st.residual == 0.0
