@@ -416,7 +416,7 @@ struct AdjStripGeo {
     static constexpr int M = (ROWS + 2 * h - 2 * R + U - 1) / U;
     static constexpr int NROW = 2 * R + M * U;                // rows streamed per wave
     static constexpr int OH = NROW - 2 * h;                   // output rows per wave
-    static constexpr int LDS = (NU + 2) * CS + ND;            // floats of LDS per wave
+    static constexpr int LDS = (NU + 2) * CS + ND + P * 64;   // floats of LDS per wave
 };
 
 struct AdjStripArgs {
@@ -474,15 +474,20 @@ __device__ __forceinline__ void adjoint_strip_step(float *ring, const AdjStripAr
     const int yend = s.Y0 + G::OH < H ? s.Y0 + G::OH : H;     // rows owned: [Y0, yend)
 
     // u ring column-major as in the forward strip: staged column c of ring
-    // row r at (c + 1) * CS + r; then the d row (lane l at l + R)
+    // row r at (c + 1) * CS + r; then the d row (lane l at l + R); then P(u) r
+    // of the last P rows (slot j, lane l at j * 64 + l), kept in LDS rather
+    // than registers: a slot is read R rows after it is written, and the
+    // register copy would cost far more VGPRs than its P values (178 -> 121 at
+    // R = 6, i.e. 2 -> 4 waves per SIMD)
     constexpr int CS = G::CS;
     float *col = ring + (lane + 1) * CS;
     float *bcol = ring + (64 + lb + 1) * CS;
     float *dw = ring + (NU + 2) * CS + lane;
+    float *prr = ring + (NU + 2) * CS + G::ND + lane;         // P(u) r, row j in slot j % P
 
-    float win[P], dwin[P], prw[P];    // x-pass u, x-pass d, P(u) r; row j in slot j % P
+    float win[P], dwin[P];            // x-pass u, x-pass d; row j in slot j % P
 #pragma unroll
-    for (int j = 0; j < P; ++j) win[j] = dwin[j] = prw[j] = 0.0f;
+    for (int j = 0; j < P; ++j) win[j] = dwin[j] = 0.0f;
     float v_m1 = 0.0f, v_m2 = 0.0f;                          // v at rows g, g-1 (before update)
     float r_m1 = 0.0f, r_0 = 0.0f;                           // r at rows g-1, g
     float txx_p = 0.0f, tyy_p = 0.0f, tyy_pp = 0.0f;         // D:A at rows g-1 (g-2 for yy)
@@ -595,7 +600,7 @@ __device__ __forceinline__ void adjoint_strip_step(float *ring, const AdjStripAr
             constexpr int kP = P;                                     // slot of row i - R - 2
             const int jd = ((R - 2 + ph) % kP + kP) % kP;
             dwin[jd] = dx;
-            prw[jd] = pr;
+            prr[jd * 64] = pr;
             tyy_pp = tyy_p;
             tyy_p = ty;
             txx_p = tx;
@@ -612,7 +617,7 @@ __device__ __forceinline__ void adjoint_strip_step(float *ring, const AdjStripAr
 #pragma unroll
                 for (int j = 0; j <= 2 * R; ++j)
                     cq = fmaf(w[j], dwin[((ph - R - 2 + j) % kP + kP) % kP], cq);
-                const float pro = prw[((ph - 2) % kP + kP) % kP];
+                const float pro = prr[((ph - 2) % kP + kP) % kP * 64];
                 const float anv = cur.oa;
                 const bool mk = cur.omk != 0;
                 const float rv = mk ? 0.0f : anv;
