@@ -294,7 +294,7 @@ def workload_throughput(eed4, torch, names=("rgb512", "scratch512_thin", "scratc
 
 def batched_vs_single(eed4, torch, cycles):
     """64 uneven images (sides U{128..1024}, 2..8% masks, sigma 1.5, lambda 0.03,
-    n 15): one eed4_inpaint_batched call (autotuned persistent kernels, graph)
+    n 15): one eed4_inpaint_batched call (autotuned queue kernels, graph)
     against 64 eed4_inpaint calls, same cycle count; throughput in
     Mpixel-updates/s and the largest RMSE between the two results."""
     from synth import WORKLOADS, make_uneven_batch

@@ -404,7 +404,7 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
             n2 += __shfl_down(n2, off, 64);
         }
         // lane 0 holds the sums; every lane stores that same value (no
-        // lane-dependent branch at the end of a persistent loop body)
+        // lane-dependent branch at the end of a batched queue-loop body)
         const double d2s = lane0_double(d2), n2s = lane0_double(n2);
         partial[0] = d2s;
         partial[1] = n2s;

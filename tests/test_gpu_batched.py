@@ -1,6 +1,6 @@
-"""Batched uneven-size inpainting (eed4_inpaint_batched): one persistent
-launch per inner step over a work queue spanning all images, cycle replayed as
-a hipGraph, per-image stop, autotuned kernel shape.
+"""Batched uneven-size inpainting (eed4_inpaint_batched): one launch per inner
+step over a work queue spanning all images, cycle replayed as a hipGraph,
+per-image stop, autotuned kernel shape.
 
 Every kernel shape must give, for each image, exactly (bitwise) what
 eed4_inpaint gives for that image alone with the same kernel family; sampled

@@ -1,11 +1,13 @@
-"""Structure of the persistent batched kernels in the gfx950 assembly (CPU
-only: hipcc cross-compiles).
+"""Structure of the batched queue kernels in the gfx950 assembly (CPU only:
+hipcc cross-compiles).
 
-Each workgroup-tile persistent kernel pulls its next tile with an atomic and
-then meets the other waves at barriers.  The pull must sit in the header block
-of the one persistent loop, and no loop nested inside it may contain a
-barrier: a nested barrier loop that skips the pull makes the waves spin on a
-stale tile index forever (regression test of that miscompilation pattern).
+Each batched kernel walks the work queue in one loop (a static stride over
+the queue); the workgroup-tile kernels meet their other waves at barriers
+inside it.  The item fetch must sit in the header block of that one loop, and
+no loop nested inside it may contain a barrier: a nested barrier loop that
+skips the fetch makes the waves spin on a stale item index forever (the
+pattern the compiler produced for an earlier atomic-counter version; kept as
+a regression test).
 """
 import os
 import re
@@ -69,8 +71,8 @@ def _loops(asm, kernel):
     return loops, atom_blocks
 
 
-def test_tile_persistent_loops(tmp_path):
-    # one persistent loop per tile kernel, no atomics, and no loop nested in it
+def test_tile_queue_loops(tmp_path):
+    # one queue loop per tile kernel, no atomics, and no loop nested in it
     # that holds a barrier (such a loop is how a lane-dependent branch near the
     # loop head once left waves spinning on a stale work index)
     asm = _assembly(tmp_path)
@@ -85,8 +87,8 @@ def test_tile_persistent_loops(tmp_path):
         assert not nested_with_barrier, (k, nested_with_barrier)
 
 
-def test_persistent_loops_exit_uniformly(tmp_path):
-    # A persistent loop must leave through a uniform (SGPR/VCC) branch: an
+def test_queue_loops_exit_uniformly(tmp_path):
+    # A queue loop must leave through a uniform (SGPR/VCC) branch: an
     # exec-mask exit (s_cbranch_execz to the kernel end) means lanes took
     # different paths around the loop, i.e. a partial wave would keep pulling.
     asm = _assembly(tmp_path)
