@@ -100,9 +100,9 @@ extern "C" {
  * Every eigenvalue stays in [0, 1], so the step bound tau <= 1/16 holds for
  * all of them.  A non-default variant runs the 60-column strip kernel of
  * shape 5 (EED4_FORCE_SHAPE may name only that shape; EED4_TILE_KERNEL is
- * EED4_EINVAL) in eed4_inpaint, eed4_fsi_cycle and eed4_fsi_step, and the
- * matching reverse step in eed4_backward; the batched entry points accept
- * only the default (EED4_EINVAL otherwise). */
+ * EED4_EINVAL) in every entry point: eed4_inpaint, eed4_fsi_cycle,
+ * eed4_fsi_step, the batched calls (no shape tuning) and, with the matching
+ * reverse step, eed4_backward. */
 #define EED4_CHARBONNIER       0
 #define EED4_PERONA_MALIK      1
 #define EED4_PERONA_MALIK_EXP  2

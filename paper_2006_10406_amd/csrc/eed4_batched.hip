@@ -64,11 +64,11 @@ __device__ __forceinline__ T *uni(T *p)
 }
 
 // Wave-strip shapes: wave w of the launch takes items w, w + nw, w + 2 nw, ...
-// (w counted in XCD-contiguous order).
-template <int R, int ROWS, bool RES, int CPL>
-__global__ __launch_bounds__(256) void bstrip_kernel(const BImage *imgs, const BItem *queue,
-                                                     const int *qlen_p, int sc, int sp, int so,
-                                                     StepArgs a, double *partials)
+// (w counted in XCD-contiguous order).  GEN: tensor variant chosen at run time.
+template <int R, int ROWS, bool RES, int CPL, bool GEN>
+__device__ __forceinline__ void bstrip_body(const BImage *imgs, const BItem *queue,
+                                            const int *qlen_p, int sc, int sp, int so,
+                                            const StepArgs &a, double *partials)
 {
     using G = StripGeo<R, ROWS, CPL>;
     __shared__ float lds[4 * G::LDS];
@@ -92,8 +92,28 @@ __global__ __launch_bounds__(256) void bstrip_kernel(const BImage *imgs, const B
         s.tau = a.tau;
         s.alpha = a.alpha;
         s.il2q = 0.25f * __int_as_float(uni(__float_as_int(d.inv_lam2)));
-        strip_step<R, RES, ROWS, CPL>(lds + wave * G::LDS, s, a.w, partials + 2 * (size_t)uni(t.slot));
+        s.model = a.model;
+        strip_step<R, RES, ROWS, CPL, GEN>(lds + wave * G::LDS, s, a.w,
+                                           partials + 2 * (size_t)uni(t.slot));
     }
+}
+
+template <int R, int ROWS, bool RES, int CPL>
+__global__ __launch_bounds__(256) void bstrip_kernel(const BImage *imgs, const BItem *queue,
+                                                     const int *qlen_p, int sc, int sp, int so,
+                                                     StepArgs a, double *partials)
+{
+    bstrip_body<R, ROWS, RES, CPL, false>(imgs, queue, qlen_p, sc, sp, so, a, partials);
+}
+
+// The tensor variants (diffusivities of Table 7, mu3 choices of Sec. 3.1) on
+// 60-column strips of >= 28 rows.
+template <int R, bool RES>
+__global__ __launch_bounds__(256) void bstrip_model_kernel(const BImage *imgs, const BItem *queue,
+                                                           const int *qlen_p, int sc, int sp,
+                                                           int so, StepArgs a, double *partials)
+{
+    bstrip_body<R, 28, RES, 1, true>(imgs, queue, qlen_p, sc, sp, so, a, partials);
 }
 
 // Workgroup-tile shapes: workgroup g takes tiles g, g + G, g + 2 G, ...
@@ -202,6 +222,16 @@ static hipError_t launch_bstep_r(int shape, int grid, const BImage *imgs, const 
     else                                                                                 \
         hipLaunchKernelGGL((bstrip_kernel<R, ROWS, false, CPL>), g, b, 0, s, imgs, queue, \
                            qlen, sc, sp, so, a, partials)
+    if (a.model != 0) {              // tensor variants: one kernel shape
+        if (shape != kShapeStripShort) return hipErrorInvalidValue;
+        if (res)
+            hipLaunchKernelGGL((bstrip_model_kernel<R, true>), g, b, 0, s, imgs, queue, qlen, sc,
+                               sp, so, a, partials);
+        else
+            hipLaunchKernelGGL((bstrip_model_kernel<R, false>), g, b, 0, s, imgs, queue, qlen, sc,
+                               sp, so, a, partials);
+        return hipGetLastError();
+    }
     switch (shape) {
     case 0: EED4_BTILE(64, 32); break;
     case 1: EED4_BTILE(64, 16); break;
@@ -276,7 +306,6 @@ static BatchLayout batch_layout(const eed4_image *im, int B, const eed4_params *
 static int check_images(const eed4_image *im, int B, const eed4_params *p)
 {
     if (!im || B < 1 || !p) return EED4_EINVAL;
-    if (model_of_flags(p->flags) != 0) return EED4_EINVAL;   // FOEED tensor only
     for (int i = 0; i < B; ++i) {
         if (!im[i].u || !im[i].mask || !im[i].known) return EED4_EINVAL;
         eed4_params q = *p;
@@ -392,7 +421,7 @@ static int enqueue_bcycle(const BatchRun &r, hipStream_t s)
     for (int k = 0; k < r.n; ++k) {
         int sc, sp, so;
         roles(k, r.n, &sc, &sp, &so);
-        StepArgs a = make_args(r.p->sigma, r.R, r.p->tau, 1.0f, k);
+        StepArgs a = make_args(r.p->sigma, r.R, r.p->tau, 1.0f, k, model_of_flags(r.p->flags));
         e = launch_bstep(r.R, r.shape, r.grid, r.dimg, r.dqueue, r.dqlen, sc, sp,
                          so, k == r.n - 1, a, r.dpartials, s);
         if (e != hipSuccess) return hip_fail(e, "batched step launch");
@@ -452,6 +481,10 @@ static int autotune(const eed4_image *im, int B, const eed4_params *p, char *bas
 static int choose_shape(const eed4_image *im, int B, const eed4_params *p, char *base,
                         const BatchLayout &L, hipStream_t s, int *shape)
 {
+    if (model_of_flags(p->flags) != 0) {   // the tensor-variant kernel
+        *shape = kShapeStripShort;
+        return EED4_OK;
+    }
     const int forced = (p->flags >> 8) & 0xff;
     if (forced) {
         if (forced > kNumShapes) return EED4_EINVAL;
@@ -484,6 +517,7 @@ extern "C" int eed4_autotune_batched(const eed4_image *imgs, int B, const eed4_p
     if (rc != EED4_OK) return rc;
     BatchLayout L = batch_layout(imgs, B, p);
     if ((rc = check_ws(ws, ws_bytes, L.total)) != EED4_OK) return rc;
+    if (model_of_flags(p->flags) != 0) return kShapeStripShort;   // one kernel for variants
     int shape = 0;
     float ms = 0.0f;
     rc = autotune(imgs, B, p, (char *)ws, L, (hipStream_t)stream, &shape, &ms);

@@ -106,8 +106,8 @@ def test_step_shape_query_without_tuning(lib):
 
 
 def test_tensor_variant_flags(lib):
-    # the variants of Table 7 / Sec. 3.1 run the 28-row strip kernels; bad fields, other
-    # shapes and the batched path are rejected before any device work
+    # the variants of Table 7 / Sec. 3.1 run the 28-row strip kernels; bad fields and other
+    # shapes are rejected before any device work, in every entry point
     import ctypes
     import paper_2006_10406_amd as e
     q = lambda p, B=1, H=300, W=200: lib.eed4_step_shape(B, H, W, ctypes.byref(p))
@@ -135,9 +135,10 @@ def test_tensor_variant_flags(lib):
     assert lib.eed4_backward(fake, fake, fake, 1, 8, 8, ctypes.byref(bad), 2, fake, fake, fake,
                              fake, 0x1000, 1 << 40, None) == EINVAL
     img = e._lib.eed4_image(fake, fake, fake, 8, 8, 0.05)
-    assert lib.eed4_inpaint_batched(ctypes.byref(img), 1, ctypes.byref(pv), 0x1000, 1 << 40,
+    assert lib.eed4_inpaint_batched(ctypes.byref(img), 1, ctypes.byref(bad), 0x1000, 1 << 40,
                                     None, None) == EINVAL
-    assert lib.eed4_batched_workspace_size(ctypes.byref(img), 1, ctypes.byref(pv)) == 0
+    assert lib.eed4_batched_workspace_size(ctypes.byref(img), 1, ctypes.byref(pv)) > 0
+    assert lib.eed4_batched_workspace_size(ctypes.byref(img), 1, ctypes.byref(bad)) == 0
 
 
 def test_strerror(lib):

@@ -141,3 +141,24 @@ def test_batch64_workload_equals_per_image_runs():
                                wl.n, M)
     print(f"batch64 image 3 {pr['u_init'].shape}: rel L2 vs FP64 {rel_l2(outs[3], ref):.3e}")
     assert rel_l2(outs[3], ref) <= 1e-5
+
+
+@pytest.mark.parametrize("d,r", [(1, 0), (2, 1), (3, 2)])
+def test_tensor_variant_batched_equals_single_images(d, r):
+    # a tensor variant (Table 7 diffusivity, Sec. 3.1 mu3 choice) through the batched queue:
+    # each image equals eed4_inpaint of it alone with the same variant, and one against the oracle
+    fl = eed4.EED4_DIFFUSIVITY(d) | eed4.EED4_MU3(r)
+    announce(f"batched tensor variant {eed4.DIFFUSIVITY_NAMES[d]}/{eed4.MU3_NAMES[r]}")
+    probs = make_images()
+    sigma, tau, n, M = 1.5, 0.05, 7, 3
+    outs, st = run_batched(probs, LAMS, eed4.params(1.0, sigma, tau, n, M, flags=fl))
+    for i, pr in enumerate(probs):
+        ref, _ = run_single(pr, LAMS[i], sigma, tau, n, M, flags=fl)
+        assert st[i].cycles == M
+        assert np.array_equal(outs[i], ref), f"image {i} {pr['u_init'].shape}"
+    i = 7
+    oref, _, _ = oracle.inpaint(probs[i]["u_init"], probs[i]["mask"], probs[i]["known"], LAMS[i],
+                                sigma, tau, n, M, diff=d, mu3=r)
+    e = rmse(outs[i], oref)
+    print(f"batched variant image {i}: RMSE vs FP64 {e:.3e}")
+    assert e <= RMSE_STEADY
