@@ -50,10 +50,13 @@ int default_step_shape(int R, int B, int H, int W);
 // Chooses one of n candidate shapes (cands[0] the default) by timing on stream
 // s.  prepare(shape) sets up a candidate outside the timed region (EED4 code);
 // launch(shape) enqueues one launch of it.  Every candidate is sampled in two
-// round-robin passes of one warm-up and two timed launches and keeps its
-// fastest time, so the clock ramp at the start of tuning does not favour the
-// candidates timed later.  A candidate replaces the current choice only when
-// it is faster by more than kTuneMargin.
+// round-robin passes of one warm-up launch and two timed samples of
+// kTuneLaunches back-to-back launches, and keeps its fastest sample, so the
+// clock ramp at the start of tuning does not favour the candidates timed later
+// and a fixed cost per launch (e.g. a profiler's) does not decide between
+// shapes a few percent apart.  A candidate replaces the current choice only
+// when it is faster by more than kTuneMargin.
+constexpr int kTuneLaunches = 4;
 template <typename Prepare, typename Launch>
 int tune_pick(const int *cands, int n, hipStream_t s, Prepare &&prepare, Launch &&launch,
               const char *where, int *best, float *best_ms)
@@ -69,7 +72,8 @@ int tune_pick(const int *cands, int n, hipStream_t s, Prepare &&prepare, Launch 
             if ((rc = prepare(cands[i])) != EED4_OK) break;
             for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
                 e = hipEventRecord(e0, s);
-                if (e == hipSuccess) e = launch(cands[i]);
+                for (int l = 0; l < (rep > 0 ? kTuneLaunches : 1) && e == hipSuccess; ++l)
+                    e = launch(cands[i]);
                 if (e == hipSuccess) e = hipEventRecord(e1, s);
                 if (e == hipSuccess) e = hipEventSynchronize(e1);
                 float ms = 0.0f;
