@@ -427,6 +427,7 @@ struct AdjStripArgs {
     float tau, alpha, il2, il3; // il2 = 1/lambda^2, il3 = 1/lambda^3
     int first;                  // k == 0: the (1-alpha) r term goes to ubar^k itself
     int model;                  // tensor variant (GEN kernels only)
+    int prio;                   // lower the issue priority along the segment
 };
 
 // Global loads of one stream row: u^k of the row, r of the row R above it,
@@ -540,6 +541,19 @@ __device__ __forceinline__ void adjoint_strip_step(float *ring, const AdjStripAr
 
 #pragma unroll 1
     for (int it = 0; it < G::M; ++it) {
+        // With every wave of the launch resident at once, waves further down
+        // their segment yield issue slots to those behind, as in the forward
+        // strip; when the launch needs more than one round of waves the host
+        // leaves this off (late waves would then hold the top priority).  Only
+        // the short segments, which small problems use, carry the code: in the
+        // 64- and 136-row kernels even the untaken branch cost 4 % at 4096^2.
+        if (ROWS <= 28 && s.prio) {
+            const int left = G::M - it;
+            if (left >= 4) __builtin_amdgcn_s_setprio(3);
+            else if (left == 3) __builtin_amdgcn_s_setprio(2);
+            else if (left == 2) __builtin_amdgcn_s_setprio(1);
+            else __builtin_amdgcn_s_setprio(0);
+        }
 #pragma unroll
         for (int ph = 0; ph < U; ++ph) {
             const int i = 2 * R + it * U + ph;               // stream row (wave-uniform)
@@ -644,7 +658,7 @@ __device__ __forceinline__ void adjoint_strip_body(const float *u_all, const flo
                                                    const uint8_t *__restrict__ mask_all, int H,
                                                    int W, int nstrip, int per_img, int nitems,
                                                    const StepArgs &a, float il3, float lam_scale,
-                                                   int first, double *lam_partials)
+                                                   int first, int prio, double *lam_partials)
 {
     using G = AdjStripGeo<R, ROWS>;
     __shared__ float lds[4 * G::LDS];
@@ -671,6 +685,7 @@ __device__ __forceinline__ void adjoint_strip_body(const float *u_all, const flo
     s.il3 = il3;
     s.first = first;
     s.model = a.model;
+    s.prio = prio;
     adjoint_strip_step<R, ROWS, GEN>(lds + wave * G::LDS, s, a.w,
                                      lam_partials + 2 * (size_t)item, lam_scale);
 }
@@ -682,10 +697,11 @@ __global__ __launch_bounds__(256) void adjoint_strip_kernel(const float *u_all, 
                                                             int H, int W, int nstrip, int per_img,
                                                             int nitems, StepArgs a, float il3,
                                                             float lam_scale, int first,
-                                                            double *lam_partials)
+                                                            int prio, double *lam_partials)
 {
     adjoint_strip_body<R, ROWS, false>(u_all, an_all, ac_all, ap_all, mask_all, H, W, nstrip,
-                                       per_img, nitems, a, il3, lam_scale, first, lam_partials);
+                                       per_img, nitems, a, il3, lam_scale, first, prio,
+                                       lam_partials);
 }
 
 // The reverse step of the tensor variants (diffusivities of Table 7, mu3
@@ -694,10 +710,10 @@ template <int R>
 __global__ __launch_bounds__(256) void adjoint_strip_model_kernel(
     const float *u_all, const float *an_all, float *ac_all, float *ap_all,
     const uint8_t *__restrict__ mask_all, int H, int W, int nstrip, int per_img, int nitems,
-    StepArgs a, float il3, float lam_scale, int first, double *lam_partials)
+    StepArgs a, float il3, float lam_scale, int first, int prio, double *lam_partials)
 {
     adjoint_strip_body<R, 28, true>(u_all, an_all, ac_all, ap_all, mask_all, H, W, nstrip,
-                                    per_img, nitems, a, il3, lam_scale, first, lam_partials);
+                                    per_img, nitems, a, il3, lam_scale, first, prio, lam_partials);
 }
 
 // ---- small helper kernels ----
@@ -836,6 +852,19 @@ static hipError_t launch_rev_tile(const RevStep &t, const StepArgs &a, float il3
     return hipGetLastError();
 }
 
+// Waves of kernel k (256-thread workgroups) the current device holds at once;
+// 0 if the runtime cannot tell.
+template <typename K>
+static long long resident_waves(K k)
+{
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, 0) != hipSuccess) return 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return 4LL * per_cu * cus;
+}
+
 template <int R, int ROWS>
 static hipError_t launch_rev_strip(const RevStep &t, const StepArgs &a, float il3, float ls,
                                    hipStream_t s)
@@ -846,9 +875,12 @@ static hipError_t launch_rev_strip(const RevStep &t, const StepArgs &a, float il
     const long long nitems = (long long)per_img * t.B;
     if (nitems > (1LL << 31) - 4) return hipErrorInvalidValue;
     const unsigned nblk = (unsigned)((nitems + 3) / 4);
+    // the issue-priority schedule only when every wave is resident at once
+    static const long long cap = resident_waves(adjoint_strip_kernel<R, ROWS>);
+    const int prio = nitems <= cap ? 1 : 0;
     hipLaunchKernelGGL((adjoint_strip_kernel<R, ROWS>), dim3(nblk), dim3(256), 0, s, t.u, t.an,
                        t.ac, t.ap, t.mask, t.H, t.W, nstrip, per_img, (int)nitems, a, il3, ls,
-                       t.first, t.lp);
+                       t.first, prio, t.lp);
     return hipGetLastError();
 }
 
@@ -862,9 +894,11 @@ static hipError_t launch_rev_model(const RevStep &t, const StepArgs &a, float il
     const long long nitems = (long long)per_img * t.B;
     if (nitems > (1LL << 31) - 4) return hipErrorInvalidValue;
     const unsigned nblk = (unsigned)((nitems + 3) / 4);
+    static const long long cap = resident_waves(adjoint_strip_model_kernel<R>);
+    const int prio = nitems <= cap ? 1 : 0;
     hipLaunchKernelGGL((adjoint_strip_model_kernel<R>), dim3(nblk), dim3(256), 0, s, t.u, t.an,
                        t.ac, t.ap, t.mask, t.H, t.W, nstrip, per_img, (int)nitems, a, il3, ls,
-                       t.first, t.lp);
+                       t.first, prio, t.lp);
     return hipGetLastError();
 }
 
