@@ -19,7 +19,8 @@ The JSON line carries:
   batched    64 uneven images: one batched call vs 64 single-image calls
   variants   fused step time of each tensor variant (Table 7 diffusivities,
              Sec. 3.1 mu3 choices) on the workload image
-  workloads  colour (channel-wise RGB) and scratch-removal inpainting, 512x512
+  workloads  colour (channel-wise RGB) and scratch-removal inpainting, 512x512,
+             and the 512x512 single image run to its relative-residual tolerance
 """
 import argparse
 import hashlib
@@ -264,7 +265,7 @@ def workload_throughput(eed4, torch, names=("rgb512", "scratch512_thin", "scratc
     """Colour (channel-wise, a batch of 3 planes) and scratch-removal workloads through
     eed4_inpaint: wl.M fixed cycles after a tuning call; pixel-updates/s counts every
     channel's pixels."""
-    from synth import WORKLOADS, make_workload_problem
+    from synth import WORKLOADS, make_problem, make_workload_problem
     res = {}
     for name in names:
         wl = WORKLOADS[name]
@@ -289,6 +290,27 @@ def workload_throughput(eed4, torch, names=("rgb512", "scratch512_thin", "scratc
         res[name] = {"mpix_updates_s": round(px * wl.n * st.cycles / (ms * 1e-3) / 1e6, 1),
                      "ms": round(ms, 3), "cycles": st.cycles, "planes": B,
                      "shape": eed4.SHAPE_NAMES[eed4.eed4_step_shape(B, wl.H, wl.W, p)]}
+    # the 512x512 single image run to the relative-residual tolerance (one host read of the
+    # residual per cycle): time to convergence
+    wl = WORKLOADS["single512"]
+    pr = make_problem(wl.H, wl.W, wl.n_ellipses, wl.ramp, wl.noise_std, wl.density, wl.seed_base)
+    mask = torch.from_numpy(pr["mask"]).cuda()
+    known = torch.from_numpy(pr["known"]).cuda()
+    u0 = torch.from_numpy(pr["u_init"]).cuda()
+    p = eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, wl.M, tol=wl.tol)
+    u = u0.clone()
+    eed4.eed4_inpaint(u, mask, known, eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, 2))
+    u = u0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, _ = eed4.eed4_inpaint(u, mask, known, p)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    res["single512_to_tol"] = {"cycles": st.cycles, "rel_residual": st.rel_residual,
+                               "ms": round(ms, 2),
+                               "mpix_updates_s": round(wl.H * wl.W * wl.n * st.cycles
+                                                       / (ms * 1e-3) / 1e6, 1),
+                               "tol": wl.tol, "cycle_len": wl.n}
     return res
 
 
