@@ -853,7 +853,9 @@ static hipError_t launch_rev_tile(const RevStep &t, const StepArgs &a, float il3
 }
 
 // Waves of kernel k (256-thread workgroups) the current device holds at once;
-// 0 if the runtime cannot tell.
+// 0 if the runtime cannot tell.  The launchers keep the first answer (the
+// devices of one node are alike); a wrong answer only switches the issue
+// priority schedule on or off, never the results.
 template <typename K>
 static long long resident_waves(K k)
 {
