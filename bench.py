@@ -49,7 +49,8 @@ def flops_per_update(R):
 # variant, least segment rows, columns per lane; or tile width and height)
 STRIP_GEOMETRY = {"strip": (64, 1), "strip_tall": (136, 1), "strip_short": (28, 1),
                   "strip_tiny": (8, 1), "strip_wide": (64, 2), "strip_wide_short": (28, 2)}
-TILE_GEOMETRY = {"tile64x32": (64, 32), "tile64x16": (64, 16), "tile32x32": (32, 32)}
+TILE_GEOMETRY = {"tile64x32": (64, 32), "tile64x16": (64, 16), "tile32x32": (32, 32),
+                 "tile32x16": (32, 16), "tile16x16": (16, 16)}
 
 
 def kernel_name(shape_name, R):

@@ -79,7 +79,7 @@ extern "C" {
  * 0: 64x32 workgroup tiles, 1: 64x16 tiles, 2: 32x32 tiles, 3: wave strips of
  * 60 columns x >= 64 rows, 4: strips of >= 136 rows, 5: strips of >= 28 rows,
  * 6: strips of >= 8 rows, 7: strips of 124 columns (two per lane) x >= 64 rows,
- * 8: 124-column strips of >= 28 rows.
+ * 8: 124-column strips of >= 28 rows, 9: 32x16 tiles, 10: 16x16 tiles.
  * All strip shapes give bitwise the same results; so do all tile shapes. */
 #define EED4_FORCE_SHAPE(s)  ((((s) + 1) & 0xff) << 8)
 

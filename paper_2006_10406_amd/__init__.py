@@ -22,7 +22,7 @@ import torch
 
 from . import _lib
 from ._lib import (EED4_ABS_TOL, EED4_ALLOW_LARGE_TAU, EED4_FORCE_SHAPE, EED4_NO_GRAPH,
-                   EED4_OP_BACKWARD, EED4_TILE_KERNEL, SHAPE_NAMES,
+                   EED4_OP_BACKWARD, EED4_TILE_KERNEL, SHAPE_NAMES, TILE_SHAPES, STRIP_SHAPES,
                    EED4_OP_CYCLE, EED4_OP_INPAINT, eed4_image, eed4_params, eed4_stats,
                    EED4_CHARBONNIER, EED4_PERONA_MALIK, EED4_PERONA_MALIK_EXP, EED4_GEMAN_REYNOLDS,
                    EED4_MU3_GEOMETRIC, EED4_MU3_ARITHMETIC, EED4_MU3_MAX, EED4_DIFFUSIVITY,
@@ -34,7 +34,7 @@ __all__ = [
     "EED4Error", "params", "eed4_radius", "eed4_workspace_size", "eed4_inpaint",
     "eed4_fsi_cycle", "eed4_fsi_step", "eed4_backward", "eed4_batched_workspace_size", "eed4_inpaint_batched",
     "eed4_strerror", "EED4_ABS_TOL", "EED4_ALLOW_LARGE_TAU", "EED4_NO_GRAPH", "EED4_TILE_KERNEL",
-    "EED4_OP_INPAINT", "EED4_OP_CYCLE", "EED4_OP_BACKWARD", "EED4_FORCE_SHAPE", "SHAPE_NAMES",
+    "EED4_OP_INPAINT", "EED4_OP_CYCLE", "EED4_OP_BACKWARD", "EED4_FORCE_SHAPE", "SHAPE_NAMES", "TILE_SHAPES", "STRIP_SHAPES",
     "eed4_autotune_batched", "eed4_step_shape", "library_path",
     "EED4_CHARBONNIER", "EED4_PERONA_MALIK", "EED4_PERONA_MALIK_EXP", "EED4_GEMAN_REYNOLDS",
     "EED4_MU3_GEOMETRIC", "EED4_MU3_ARITHMETIC", "EED4_MU3_MAX", "EED4_DIFFUSIVITY", "EED4_MU3",

@@ -202,8 +202,8 @@ static void item_dims(int shape, int R, int *iw, int *ih)
         *ih = strip_rows(R, shape);
         return;
     }
-    *iw = kTileShapes[shape].tw;
-    *ih = kTileShapes[shape].th;
+    *iw = kTileShapes[tile_index(shape)].tw;
+    *ih = kTileShapes[tile_index(shape)].th;
 }
 
 template <int R>
@@ -242,6 +242,8 @@ static hipError_t launch_bstep_r(int shape, int grid, const BImage *imgs, const 
     case kShapeStripTiny: EED4_BSTRIP(8, 1); break;
     case kShapeStripWide: EED4_BSTRIP(64, 2); break;
     case kShapeStripWideShort: EED4_BSTRIP(28, 2); break;
+    case kShapeTile32x16: EED4_BTILE(32, 16); break;
+    case kShapeTile16x16: EED4_BTILE(16, 16); break;
     default: return hipErrorInvalidValue;
     }
 #undef EED4_BTILE

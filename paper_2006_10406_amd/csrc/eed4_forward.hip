@@ -164,7 +164,7 @@ int tiles_per_image(int shape, int R, int H, int W)
         if (oh <= 0) return 0;
         return ((W + sw - 1) / sw) * ((H + oh - 1) / oh);
     }
-    const TileShape ts = kTileShapes[shape];
+    const TileShape ts = kTileShapes[tile_index(shape)];
     return ((W + ts.tw - 1) / ts.tw) * ((H + ts.th - 1) / ts.th);
 }
 
@@ -235,6 +235,8 @@ static hipError_t launch_step_r(int shape, const float *ucur, const float *uprev
     case kShapeStripTiny: return launch_strip_t<R, 8>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
     case kShapeStripWide: return launch_strip_t<R, 64, 2>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
     case kShapeStripWideShort: return launch_strip_t<R, 28, 2>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
+    case kShapeTile32x16: return launch_step_t<R, 32, 16>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
+    case kShapeTile16x16: return launch_step_t<R, 16, 16>(ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
     default: return hipErrorInvalidValue;
     }
 }

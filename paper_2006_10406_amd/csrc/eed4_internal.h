@@ -32,19 +32,25 @@ struct TileShape {
     int tw, th;
 };
 
-// Kernel shapes compiled into the library (index = config id): 0..2 are
-// workgroup tiles (tw x th outputs per 256-thread workgroup); 3..8 are
-// wave strips (60 or 124 columns x a segment of rows per wave).
-constexpr int kNumTileShapes = 3;
-constexpr TileShape kTileShapes[kNumTileShapes] = {{64, 32}, {64, 16}, {32, 32}};
+// Kernel shapes compiled into the library (index = config id): 0..2 and
+// 9..10 are workgroup tiles (tw x th outputs per 256-thread workgroup); 3..8
+// are wave strips (60 or 124 columns x a segment of rows per wave).  The
+// small tiles (9, 10) give images of a few hundred pixels a side more
+// workgroups than the chip has CUs.
+constexpr int kNumTileShapes = 5;
+constexpr TileShape kTileShapes[kNumTileShapes] = {{64, 32}, {64, 16}, {32, 32}, {32, 16}, {16, 16}};
 constexpr int kShapeStrip = 3;       // wave strips of >= 64 output rows
 constexpr int kShapeStripTall = 4;   // >= 136 rows
 constexpr int kShapeStripShort = 5;  // >= 28 rows (more waves for small images)
 constexpr int kShapeStripTiny = 6;   // >= 8 rows (shortest row pipeline per wave)
 constexpr int kShapeStripWide = 7;       // two columns per lane (124 per wave), >= 64 rows
 constexpr int kShapeStripWideShort = 8;  // two columns per lane, >= 28 rows
-constexpr int kNumShapes = 9;
-constexpr bool is_strip(int shape) { return shape >= kShapeStrip && shape < kNumShapes; }
+constexpr int kShapeTile32x16 = 9;
+constexpr int kShapeTile16x16 = 10;
+constexpr int kNumShapes = 11;
+constexpr bool is_strip(int shape) { return shape >= kShapeStrip && shape <= kShapeStripWideShort; }
+// index into kTileShapes of a tile shape
+constexpr int tile_index(int shape) { return shape < kShapeStrip ? shape : shape - 6; }
 constexpr int strip_target_rows(int shape)
 {
     return shape == kShapeStripTall ? 136

@@ -268,9 +268,9 @@ def test_every_step_shape_and_the_autotuned_default(H, W, B):
         eed4.eed4_inpaint(u, to_dev(b["mask"]), to_dev(b["known"]),
                           eed4.params(0.03, 1.5, 0.05, 9, 2, flags=flags))
         outs[shape] = u.cpu().numpy()
-    for sh in (1, 2):
+    for sh in eed4.TILE_SHAPES:
         assert np.array_equal(outs[sh], outs[0])       # tile shapes: same arithmetic
-    for sh in range(4, len(eed4.SHAPE_NAMES)):
+    for sh in eed4.STRIP_SHAPES:
         assert np.array_equal(outs[sh], outs[3])       # strip heights: same arithmetic
     assert rel_l2(outs[3], outs[0]) <= 1e-6
     assert np.array_equal(outs[None], outs[0]) or np.array_equal(outs[None], outs[3])
