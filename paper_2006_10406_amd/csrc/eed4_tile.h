@@ -130,6 +130,30 @@ __device__ __forceinline__ void step_tile(float *smem, const float *ucur, const 
     const int tid = threadIdx.x;
     const int gx0 = tx * TW, gy0 = ty * TH;
 
+    // The pointwise operands of this thread's outputs (stage E: rows rr,
+    // rr + RPP, ... of column c) are loaded first, so that their memory
+    // latency overlaps stages A-D instead of following them.  Tiles with
+    // more than 4 outputs per thread load them in stage E (the registers
+    // would cost more waves than the latency they hide).
+    constexpr int NE = TH / G::RPP;
+    constexpr bool PF = NE <= 4;
+    const int c = tid % TW, rr = tid / TW;
+    float ek[NE], ep[NE], ef[NE];
+    int em[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+        const int gy = gy0 + rr + e * G::RPP, gx = gx0 + c;
+        ek[e] = ep[e] = ef[e] = 0.0f;
+        em[e] = 0;
+        if (PF && gy < H && gx < W) {
+            const size_t gi = (size_t)gy * W + gx;
+            ek[e] = ucur[gi];
+            ep[e] = uprev[gi];
+            em[e] = mask[gi];
+            if (ref) ef[e] = ref[gi];
+        }
+    }
+
     // ---- A: u^k with halo ----
     {
         const int x0 = gx0 - G::h, y0 = gy0 - G::h;
@@ -227,9 +251,9 @@ __device__ __forceinline__ void step_tile(float *smem, const float *ucur, const 
 
     // ---- E: outer differences, FSI step, Dirichlet hold, residual ----
     double d2 = 0.0, n2 = 0.0;
-    const int c = tid % TW, rr = tid / TW;
-#pragma unroll 2
-    for (int r = rr; r < TH; r += G::RPP) {
+#pragma unroll(PF ? NE : 2)
+    for (int e = 0; e < NE; ++e) {
+        const int r = rr + e * G::RPP;
         int gy = gy0 + r, gx = gx0 + c;
         if (gy < H && gx < W) {
             int p = (r + 1) * G::PW + (c + 1);
@@ -240,13 +264,13 @@ __device__ __forceinline__ void step_tile(float *smem, const float *ucur, const 
                        ((Tyy[-G::PW] - Tyy[0]) + (Tyy[G::PW] - Tyy[0])) +
                        0.5f * ((Txy[G::PW + 1] + Txy[-G::PW - 1]) - (Txy[G::PW - 1] + Txy[-G::PW + 1]));
             size_t gi = (size_t)gy * W + gx;
-            float uk = ucur[gi];
-            float up = uprev[gi];
+            float uk = PF ? ek[e] : ucur[gi];
+            float up = PF ? ep[e] : uprev[gi];
             float wv = fmaf(-tau, pu, uk);
             float un = fmaf(alpha, wv - up, up);
-            if (mask[gi]) un = uk;
+            if (PF ? em[e] : mask[gi]) un = uk;
             if (ref) {
-                double dd = (double)un - (double)ref[gi];
+                double dd = (double)un - (double)(PF ? ef[e] : ref[gi]);
                 d2 = fma(dd, dd, d2);
                 n2 = fma((double)un, (double)un, n2);
             }
