@@ -251,7 +251,8 @@ __device__ __forceinline__ void step_tile(float *smem, const float *ucur, const 
 
     // ---- E: outer differences, FSI step, Dirichlet hold, residual ----
     double d2 = 0.0, n2 = 0.0;
-#pragma unroll(PF ? NE : 2)
+    constexpr int UE = PF ? NE : 2;
+#pragma unroll UE
     for (int e = 0; e < NE; ++e) {
         const int r = rr + e * G::RPP;
         int gy = gy0 + r, gx = gx0 + c;
