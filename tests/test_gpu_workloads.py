@@ -4,14 +4,15 @@ FP64 oracle, through the C ABI.
 The paper inpaints RGB images channel-wise (Sec. 4.1) and removes thin (6 %)
 and thick (18 %) scratches (Sec. 4.2).  Here a colour image is an equal-size
 batch of three planes sharing one mask, and a scratch mask is a structured
-mask with most pixels known.  Bar: relative L2 <= 1e-5 per cycle from the
+mask with most pixels known.  Both also go through the uneven-batch call
+beside images of other sizes.  Bar: relative L2 <= 1e-5 per cycle from the
 oracle's state, RMSE <= 1e-4 at equal cycle counts.
 """
 import numpy as np
 import pytest
 
 import oracle
-from synth import WORKLOADS, make_rgb_problem, make_workload_problem
+from synth import WORKLOADS, make_rgb_problem, make_scratch_problem, make_workload_problem
 from tests.helpers import REL_L2_PER_CYCLE, RMSE_STEADY, announce, rel_l2, rmse, to_dev
 
 pytestmark = pytest.mark.gpu
@@ -94,3 +95,35 @@ def test_scratch_removal_full_size(name):
     assert e <= RMSE_STEADY
     assert np.allclose(hist[:, 0, 1], rh[:, 1], rtol=1e-5)
     assert np.array_equal(got[~unk], pr["known"][~unk])
+
+
+@pytest.mark.parametrize("shape", [2, 5, 10])
+def test_colour_and_scratch_images_in_one_uneven_batch(shape):
+    # three colour planes sharing one mask, a thin and a thick scratch image of other sizes, in
+    # one eed4_inpaint_batched call: each equals its own eed4_inpaint run in the same kernel
+    # shape bitwise, and one plane meets the oracle bar
+    sigma, tau, n, M = 1.5, 0.05, 8, 4
+    announce(f"colour + scratch uneven batch, shape {eed4.SHAPE_NAMES[shape]}, {M} cycles of {n}")
+    rgb = make_rgb_problem(120, 150, 10, True, 0.01, 0.05, 6200)
+    thin = make_scratch_problem(130, 97, 10, True, 0.005, 0.06, 2, 6201)
+    thick = make_scratch_problem(88, 170, 10, True, 0.005, 0.18, 6, 6202)
+    probs = [{k: rgb[k][c] for k in ("mask", "known", "u_init")} for c in range(3)]
+    probs += [thin, thick]
+    lams = [0.03, 0.03, 0.03, 0.02, 0.04]
+    flags = eed4.EED4_FORCE_SHAPE(shape)
+    us = [to_dev(pr["u_init"]) for pr in probs]
+    st = eed4.eed4_inpaint_batched([(u, to_dev(pr["mask"]), to_dev(pr["known"]), lam)
+                                    for u, pr, lam in zip(us, probs, lams)],
+                                   eed4.params(1.0, sigma, tau, n, M, flags=flags))
+    torch.cuda.synchronize()
+    for i, (u, pr, lam) in enumerate(zip(us, probs, lams)):
+        v = to_dev(pr["u_init"])
+        eed4.eed4_inpaint(v, to_dev(pr["mask"]), to_dev(pr["known"]),
+                          eed4.params(lam, sigma, tau, n, M, flags=flags))
+        assert st[i].cycles == M
+        assert torch.equal(u, v), f"image {i} {tuple(u.shape)}"
+    ref, _, _ = oracle.inpaint(probs[4]["u_init"], probs[4]["mask"], probs[4]["known"], lams[4],
+                               sigma, tau, n, M)
+    e = rmse(us[4].cpu().numpy(), ref)
+    print(f"thick scratch {eed4.SHAPE_NAMES[shape]}: RMSE vs FP64 {e:.3e}")
+    assert e <= RMSE_STEADY
