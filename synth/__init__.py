@@ -6,7 +6,9 @@ from it without sharing any part of the method.
 
 Images are piecewise smooth: filled ellipses over a uniform background,
 optionally blended with a linear ramp, plus Gaussian noise, clipped to [0, 1].
-Masks keep an exact number of uniformly drawn pixels.  These stand in for the
+Masks keep an exact number of uniformly drawn pixels (the device-side
+generator for images too large for the host draws a Bernoulli mask).  These
+stand in for the
 paper's natural and medical test images (Sec. 4), which are not available.
 """
 from .generator import (
@@ -14,6 +16,7 @@ from .generator import (
     make_image,
     make_mask,
     make_problem,
+    make_problem_device,
     make_batch,
     make_uneven_batch,
     make_rgb_problem,
@@ -29,6 +32,7 @@ __all__ = [
     "make_image",
     "make_mask",
     "make_problem",
+    "make_problem_device",
     "make_batch",
     "make_uneven_batch",
     "make_rgb_problem",

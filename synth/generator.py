@@ -303,3 +303,62 @@ def make_workload_problem(wl: Workload) -> dict:
         return make_scratch_problem(wl.H, wl.W, wl.n_ellipses, wl.ramp, wl.noise_std,
                                     wl.density, SCRATCH_WIDTH[wl.name], wl.seed_base)
     raise ValueError(f"{wl.name} is not a colour or scratch workload")
+
+
+def make_problem_device(H: int, W: int, n_ellipses: int, ramp: bool, noise_std: float,
+                        density: float, seed: int, device="cuda", chunk_rows: int = 2048) -> dict:
+    """The recipe of ``make_problem`` drawn on a torch device, for images too
+    large to draw on the host (up to 2^31 pixels).  Ellipse and ramp
+    parameters come from ``numpy.random.default_rng(seed)`` as on the host;
+    the per-pixel noise and the mask come from a ``torch.Generator`` on the
+    device seeded with ``seed``, in blocks of ``chunk_rows`` rows.  The mask
+    keeps each pixel independently with probability ``density`` (a Bernoulli
+    mask rather than an exact count).  Returns float32 ``u_init`` and
+    ``known`` and a uint8 ``mask`` on the device (no ground-truth copy)."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    img = torch.full((H, W), float(rng.uniform(0.0, 1.0)), dtype=torch.float32, device=device)
+    m = float(min(H, W))
+    for _ in range(n_ellipses):
+        cy, cx = rng.uniform(0.0, H), rng.uniform(0.0, W)
+        a, b = rng.uniform(0.05, 0.3) * m, rng.uniform(0.05, 0.3) * m
+        th, grey = rng.uniform(0.0, np.pi), rng.uniform(0.0, 1.0)
+        rad = max(a, b)
+        y0, y1 = max(0, int(np.floor(cy - rad))), min(H, int(np.ceil(cy + rad)) + 1)
+        x0, x1 = max(0, int(np.floor(cx - rad))), min(W, int(np.ceil(cx + rad)) + 1)
+        if y0 >= y1 or x0 >= x1:
+            continue
+        c, s = float(np.cos(th)), float(np.sin(th))
+        xx = torch.arange(x0, x1, dtype=torch.float32, device=device)[None, :] - cx
+        for r0 in range(y0, y1, chunk_rows):
+            r1 = min(y1, r0 + chunk_rows)
+            yy = torch.arange(r0, r1, dtype=torch.float32, device=device)[:, None] - cy
+            p = (xx * c + yy * s) / a
+            q = (-xx * s + yy * c) / b
+            img[r0:r1, x0:x1].masked_fill_(p * p + q * q <= 1.0, grey)
+    phi = rng.uniform(0.0, 2.0 * np.pi) if ramp else 0.0
+    cu, su = np.cos(phi) / W, np.sin(phi) / H
+    corners = [x * cu + y * su for y in (0, H - 1) for x in (0, W - 1)]
+    lo, hi = min(corners), max(corners)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    mask = torch.empty((H, W), dtype=torch.uint8, device=device)
+    xs = torch.arange(W, dtype=torch.float32, device=device)[None, :] * cu
+    for r0 in range(0, H, chunk_rows):
+        r1 = min(H, r0 + chunk_rows)
+        blk = img[r0:r1]
+        if ramp and hi > lo:
+            ys = torch.arange(r0, r1, dtype=torch.float32, device=device)[:, None] * su
+            blk.mul_(0.75).add_(((xs + ys) - lo) * (0.25 / (hi - lo)))
+        if noise_std > 0:
+            blk.add_(torch.randn(blk.shape, generator=gen, device=device) * noise_std)
+        blk.clamp_(0.0, 1.0)
+        mask[r0:r1] = (torch.rand(blk.shape, generator=gen, device=device) < density).to(torch.uint8)
+    km = mask != 0
+    n_known = int(km.sum())
+    fill = float((img * km).sum(dtype=torch.float64) / n_known) if n_known else 0.5
+    known = torch.where(km, img, torch.zeros((), device=device))
+    img.masked_fill_(~km, fill)            # img becomes u_init
+    del km
+    return {"u_init": img, "mask": mask, "known": known, "seed": seed}

@@ -2,8 +2,8 @@
 seed, the mask recipes (coverage, shared colour mask) and the initial guess."""
 import numpy as np
 
-from synth import (SCRATCH_WIDTH, WORKLOADS, make_rgb_problem, make_scratch_mask,
-                   make_workload_problem)
+from synth import (SCRATCH_WIDTH, WORKLOADS, make_problem_device, make_rgb_problem,
+                   make_scratch_mask, make_workload_problem)
 
 
 def test_rgb_problem_channels_share_one_mask():
@@ -52,3 +52,22 @@ def test_workload_problems():
             assert p["image"].shape == (wl.H, wl.W)
             assert wl.density <= 1.0 - p["mask"].mean() <= wl.density + 0.03
             assert SCRATCH_WIDTH[name] in (2, 6)
+
+
+def test_device_generator_recipe_on_the_cpu_device():
+    # the torch-side generator of very large problems, run on the CPU device: seeded, values in
+    # [0, 1], Bernoulli mask near its density, known values on the mask and their mean elsewhere
+    import torch
+    a = make_problem_device(257, 389, 12, True, 0.01, 0.04, 5, device="cpu", chunk_rows=50)
+    b = make_problem_device(257, 389, 12, True, 0.01, 0.04, 5, device="cpu", chunk_rows=50)
+    assert all(torch.equal(a[k], b[k]) for k in ("u_init", "mask", "known"))
+    u, m, f = a["u_init"], a["mask"], a["known"]
+    assert u.dtype == torch.float32 and m.dtype == torch.uint8 and u.shape == (257, 389)
+    assert abs(float(m.float().mean()) - 0.04) < 0.01
+    km = m != 0
+    assert torch.equal(u[km], f[km]) and bool((f[~km] == 0).all())
+    assert float(u.min()) >= 0.0 and float(u.max()) <= 1.0
+    fill = float(f[km].double().mean())
+    assert torch.allclose(u[~km].double(), torch.full_like(u[~km].double(), fill), rtol=1e-6)
+    assert not torch.equal(make_problem_device(64, 64, 3, False, 0.01, 0.05, 6, device="cpu")["mask"],
+                           make_problem_device(64, 64, 3, False, 0.01, 0.05, 7, device="cpu")["mask"])
