@@ -535,6 +535,9 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": f"{kname} (fused FSI step)",
                      "kernel_us": round(kms * 1e3, 2),
+                     # the timed region per fused-step launch (it also holds one residual
+                     # reduction per cycle): agrees with kernel_us to a few percent
+                     "timed_region_us_per_launch": round(ms * 1e3 / (args.steps * n), 2),
                      "algorithmic_bytes_per_launch": per_launch_bytes,
                      "alu": {"achieved": round(tflops, 2), "peak": round(ALU_PEAK_TFLOPS, 1),
                              "unit": "TFLOP/s", "frac": round(tflops / ALU_PEAK_TFLOPS, 4),
