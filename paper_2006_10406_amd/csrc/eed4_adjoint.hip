@@ -810,7 +810,7 @@ static int adj_items_r(int shape, int H, int W)
     default: break;                                                                 \
     }
 
-// Work items per image of a reverse step: tiles (shapes 0..2, one adjoint
+// Work items per image of a reverse step: tiles (every tile shape, one adjoint
 // tile shape) or strip segments of the given height.
 static int adjoint_items(int R, int shape, int H, int W)
 {
