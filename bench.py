@@ -396,8 +396,8 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100, help="timed FSI cycles")
-    ap.add_argument("--warmup", type=int, default=30,
-                    help="untimed FSI cycles (the GPU clock needs some tens of ms of work to settle)")
+    ap.add_argument("--warmup", type=int, default=300,
+                    help="untimed FSI cycles (the GPU clock needs a few hundred ms of sustained work to settle)")
     ap.add_argument("--kernel-reps", type=int, default=20,
                     help="cycles of back-to-back eed4_fsi_step launches for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -439,7 +439,8 @@ def main():
     H, W, n = wl.H, wl.W, wl.n
     pw = eed4.params(wl.lam, wl.sigma, wl.tau, n, max(args.warmup, 1))
     pt = eed4.params(wl.lam, wl.sigma, wl.tau, n, args.steps)
-    wsv = aligned_workspace(torch, eed4.eed4_workspace_size(eed4.EED4_OP_INPAINT, 1, H, W, pt), dev)
+    wsv = aligned_workspace(torch, max(eed4.eed4_workspace_size(eed4.EED4_OP_INPAINT, 1, H, W, q)
+                                       for q in (pw, pt)), dev)
 
     if args.probe:
         probe(eed4, torch, u_init, mask, wl)
