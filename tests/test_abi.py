@@ -89,6 +89,17 @@ def test_argument_errors_before_any_gpu_work(lib):
     assert _call_inpaint(lib, big, ws=0) == e._lib.EED4_EWORKSPACE
 
 
+def test_shape_families_partition_the_shape_ids():
+    # every shape id is a tile or a strip shape, never both (results are bitwise equal within a
+    # family); the names follow the family
+    import paper_2006_10406_amd as e
+    ids = set(range(len(e.SHAPE_NAMES)))
+    assert set(e.TILE_SHAPES) | set(e.STRIP_SHAPES) == ids
+    assert not set(e.TILE_SHAPES) & set(e.STRIP_SHAPES)
+    assert all(e.SHAPE_NAMES[i].startswith("tile") for i in e.TILE_SHAPES)
+    assert all(e.SHAPE_NAMES[i].startswith("strip") for i in e.STRIP_SHAPES)
+
+
 def test_step_shape_query_without_tuning(lib):
     # no device work: forced shapes, the tile flag and the size rule used
     # before any tuning (strips when they give enough waves, else 32x32 tiles)
