@@ -233,7 +233,6 @@ int eed4_inpaint_batched(const eed4_image *imgs, int B, const eed4_params *p,
 int eed4_autotune_batched(const eed4_image *imgs, int B, const eed4_params *p,
                           void *ws, size_t ws_bytes, void *stream);
 
-/* Message for a return code. */
 /* Fused-step kernel shape (EED4_FORCE_SHAPE index) that eed4_inpaint,
  * eed4_fsi_cycle and eed4_fsi_step use for B equal-size H x W images with
  * parameters p: the forced shape, else the one the autotuner chose for this
@@ -242,6 +241,7 @@ int eed4_autotune_batched(const eed4_image *imgs, int B, const eed4_params *p,
  * (>= 0) or EED4_EINVAL. */
 int eed4_step_shape(int B, int H, int W, const eed4_params *p);
 
+/* Message for a return code (static or thread-local storage; not freed). */
 const char *eed4_strerror(int code);
 
 #ifdef __cplusplus
