@@ -212,6 +212,83 @@ def test_fsi_cycle_matches_dct_prediction(n, cycles):
     assert np.abs(u - ref).max() <= 1e-11
 
 
+def predicted_history(u0, n, tau, M):
+    """Cycle residuals of the g == 1, mask-free evolution from the DCT closed form.
+
+    Cycle m multiplies DCT mode (k, l) by p_n(1 - tau rho_kl) (Sec. 3.3 FSI
+    recursion), and the orthonormal DCT keeps 2-norms, so with X = DCT(u0):
+    ||u^{m+1,0} - u^{m,0}|| = ||(p^{m+1} - p^m) X|| and ||u^{m+1,0}|| = ||p^{m+1} X||.
+    Returns [M, 2] of (residual, norm)."""
+    H, W = u0.shape
+    X = mo.scipy.fft.dctn(u0, type=2, norm="ortho")
+    p = fsi_polynomial(n, 1 - tau * mo.biharmonic_symbol(H, W))
+    out = np.zeros((M, 2))
+    for m in range(M):
+        out[m, 0] = np.linalg.norm((p ** (m + 1) - p ** m) * X)
+        out[m, 1] = np.linalg.norm(p ** (m + 1) * X)
+    return out
+
+
+def test_residual_history_matches_dct_closed_form():
+    # the per-cycle residual and norm that the stop rule of Sec. 3.3 reads, against the
+    # closed form of the linear (g == 1) evolution without known pixels
+    H, W, n, tau, M = 11, 13, 10, 0.05, 25
+    u0 = RNG.uniform(0, 1, (H, W))
+    _, cyc, hist = oracle.inpaint(u0, np.zeros((H, W), np.uint8), np.zeros((H, W)), 1e12, 1.0,
+                                  tau, n, M)
+    ref = predicted_history(u0, n, tau, M)
+    assert cyc == M
+    assert np.allclose(hist, ref, rtol=1e-11, atol=1e-14)
+
+
+@pytest.mark.parametrize("abs_tol", [False, True])
+@pytest.mark.parametrize("stop_at", [1, 4, 9])
+def test_stop_rule_is_first_cycle_below_tol(abs_tol, stop_at):
+    # Sec. 3.3: stop after the FIRST cycle whose residual is below tol (relative to
+    # ||u^{m,n}|| by default, plain with abs_tol).  tol is set halfway between the
+    # predicted criterion of cycle stop_at and the smallest of the cycles before it, so
+    # an oracle that stops a cycle early or late, or tests the wrong norm, fails.
+    H, W, n, tau, M = 12, 9, 8, 0.05, 40
+    u0 = RNG.uniform(0, 1, (H, W))
+    ref = predicted_history(u0, n, tau, M)
+    crit = ref[:, 0] if abs_tol else ref[:, 0] / ref[:, 1]
+    before = crit[:stop_at].min()
+    assert crit[stop_at] < before
+    tol = 0.5 * (crit[stop_at] + before)
+    # with the other norm the rule would stop at a different cycle
+    other = ref[:, 0] / ref[:, 1] if abs_tol else ref[:, 0]
+    assert int(np.argmax(other < tol)) != stop_at
+    _, cyc, hist = oracle.inpaint(u0, np.zeros((H, W), np.uint8), np.zeros((H, W)), 1e12, 1.0,
+                                  tau, n, M, tol=tol, abs_tol=abs_tol)
+    assert cyc == stop_at + 1
+    assert hist.shape == (stop_at + 1, 2)
+    assert np.allclose(hist, ref[:stop_at + 1], rtol=1e-11, atol=1e-14)
+
+
+def test_batch_stop_rule_waits_for_every_image():
+    # an equal-size batch stops at the first cycle where every image's relative residual is
+    # below tol: the slower image decides
+    H, W, n, tau, M = 10, 10, 6, 0.05, 60
+    fast = RNG.uniform(0, 1, (H, W))
+    slow = np.add.outer(np.linspace(0, 1, H), np.linspace(0, 0.5, W)) + 0.01 * RNG.normal(size=(H, W))
+    rf = predicted_history(fast, n, tau, M)
+    rs = predicted_history(slow, n, tau, M)
+    worst = np.maximum(rf[:, 0] / rf[:, 1], rs[:, 0] / rs[:, 1])
+    c = 6
+    assert worst[c] < worst[:c].min()
+    tol = 0.5 * (worst[c] + worst[:c].min())
+    first_fast = int(np.argmax(rf[:, 0] / rf[:, 1] < tol))
+    first_slow = int(np.argmax(rs[:, 0] / rs[:, 1] < tol))
+    assert first_fast != first_slow        # the two images alone would stop at different cycles
+    u0 = np.stack([fast, slow])
+    z = np.zeros((2, H, W))
+    _, cyc, hist = oracle.inpaint(u0, np.zeros((2, H, W), np.uint8), z, 1e12, 1.0, tau, n, M,
+                                  tol=tol)
+    assert cyc == c + 1
+    assert np.allclose(hist[:, 0], rf[:c + 1], rtol=1e-11, atol=1e-14)
+    assert np.allclose(hist[:, 1], rs[:c + 1], rtol=1e-11, atol=1e-14)
+
+
 # ---------------------------------------------------------------- P7 symmetries
 def small_problem(H=14, W=13, density=0.15, seed=7):
     rng = np.random.default_rng(seed)
