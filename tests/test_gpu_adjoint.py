@@ -4,14 +4,15 @@ torch.autograd wrapper.
 
 Both adjoints differentiate the same trajectory: the oracle recomputes each
 cycle in FP64 from the checkpoints the GPU forward wrote.  Bar: relative L2
-<= 1e-4 for dL/df on the mask, dL/du_init off the mask, and dL/dlambda.
+<= 1e-4 and every element within 1e-4 of the largest oracle value, for dL/df
+on the mask, dL/du_init off the mask, and dL/dlambda.
 """
 import numpy as np
 import pytest
 
 import oracle
 from synth import WORKLOADS, make_batch, make_problem
-from tests.helpers import announce, rel_l2, to_dev
+from tests.helpers import announce, assert_grad_parity, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -20,8 +21,6 @@ if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 import paper_2006_10406_amd as eed4  # noqa: E402
 from paper_2006_10406_amd import autograd as ea  # noqa: E402
-
-ADJ_TOL = 1e-4
 
 
 def gpu_forward_backward(b, lam, sigma, tau, n, M, gu, flags=0):
@@ -44,13 +43,11 @@ def compare(b, ck, gk, gi, gl, lam, sigma, tau, n, gu, label):
     ogk, ogi, ogl = oracle.backward(ck.astype(np.float64), b["mask"], b["known"], lam, sigma, tau,
                                     n, gu)
     m = b["mask"] != 0
-    ek = rel_l2(gk[m], ogk[m])
-    ei = rel_l2(gi[~m], ogi[~m])
-    el = rel_l2(gl, ogl)
-    print(f"{label}: rel L2 dL/df {ek:.3e}, dL/du_init {ei:.3e}, dL/dlambda {el:.3e} "
-          f"(gpu {gl[:2]}, oracle {ogl[:2]})")
+    print(f"{label}: dL/dlambda gpu {gl[:2]}, oracle {np.atleast_1d(ogl)[:2]}")
     assert np.all(gk[~m] == 0) and np.all(gi[m] == 0)
-    assert ek <= ADJ_TOL and ei <= ADJ_TOL and el <= ADJ_TOL
+    assert_grad_parity(gk[m], ogk[m], f"{label} dL/df")
+    assert_grad_parity(gi[~m], ogi[~m], f"{label} dL/du_init")
+    assert_grad_parity(gl, ogl, f"{label} dL/dlambda")
 
 
 @pytest.mark.parametrize("H,W,sigma,lam,n,M", [

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 from synth import WORKLOADS, make_problem, make_uneven_batch
-from tests.helpers import RMSE_STEADY, announce, rel_l2, rmse, to_dev
+from tests.helpers import REL_L2_PER_CYCLE, announce, assert_steady_parity, rel_l2, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -119,9 +119,8 @@ def test_batched_against_oracle():
     for i in (1, 2, 5, 7):
         pr = probs[i]
         ref, _, _ = oracle.inpaint(pr["u_init"], pr["mask"], pr["known"], LAMS[i], sigma, tau, n, M)
-        e = rmse(outs[i], ref)
-        print(f"image {i} {pr['u_init'].shape}: RMSE vs FP64 {e:.3e}, rel L2 {rel_l2(outs[i], ref):.3e}")
-        assert e <= RMSE_STEADY and rel_l2(outs[i], ref) <= 1e-5
+        assert_steady_parity(outs[i], ref, f"image {i} {pr['u_init'].shape}")
+        assert rel_l2(outs[i], ref) <= REL_L2_PER_CYCLE
 
 
 def test_batch64_workload_equals_per_image_runs():
@@ -139,8 +138,8 @@ def test_batch64_workload_equals_per_image_runs():
     pr = probs[3]
     ref, _, _ = oracle.inpaint(pr["u_init"], pr["mask"], pr["known"], wl.lam, wl.sigma, wl.tau,
                                wl.n, M)
-    print(f"batch64 image 3 {pr['u_init'].shape}: rel L2 vs FP64 {rel_l2(outs[3], ref):.3e}")
-    assert rel_l2(outs[3], ref) <= 1e-5
+    assert_steady_parity(outs[3], ref, f"batch64 image 3 {pr['u_init'].shape}")
+    assert rel_l2(outs[3], ref) <= REL_L2_PER_CYCLE
 
 
 @pytest.mark.parametrize("d,r", [(1, 0), (2, 1), (3, 2)])
@@ -159,6 +158,4 @@ def test_tensor_variant_batched_equals_single_images(d, r):
     i = 7
     oref, _, _ = oracle.inpaint(probs[i]["u_init"], probs[i]["mask"], probs[i]["known"], LAMS[i],
                                 sigma, tau, n, M, diff=d, mu3=r)
-    e = rmse(outs[i], oref)
-    print(f"batched variant image {i}: RMSE vs FP64 {e:.3e}")
-    assert e <= RMSE_STEADY
+    assert_steady_parity(outs[i], oref, f"batched variant image {i}")

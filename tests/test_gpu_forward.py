@@ -1,16 +1,19 @@
 """Parity of the fused HIP forward path (eed4_fsi_cycle, eed4_inpaint) with
 the FP64 oracle, through the C ABI.
 
-Bar: relative L2 <= 1e-5 for one FSI cycle started from the same FP32 state,
-RMSE <= 1e-4 for multi-cycle runs at equal cycle counts; the FP32-vs-FP64
-error of every case is printed.  Inputs come from the seeded generator.
+Bar: relative L2 <= 1e-5 and every element within 1e-5 for one FSI cycle
+started from the same FP32 state; RMSE <= 1e-4 and every element within 1e-4
+for multi-cycle runs at equal cycle counts (grey values in [0, 1]).  The
+FP32-vs-FP64 error of every case is printed.  Inputs come from the seeded
+generator.
 """
 import numpy as np
 import pytest
 
 import oracle
 from synth import WORKLOADS, make_batch, make_problem
-from tests.helpers import REL_L2_PER_CYCLE, RMSE_STEADY, announce, rel_l2, rmse, to_dev
+from tests.helpers import (announce, assert_cycle_parity, assert_steady_parity, rel_l2, rmse,
+                           to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -50,9 +53,8 @@ def test_small64_per_cycle_parity():
     knowns = np.repeat(pr["known"][None], M, 0)
     got, sums = gpu_cycle(ck, masks, knowns, wl.lam, wl.sigma, wl.tau, wl.n)
     ref, rh = oracle_cycle(ck, masks, knowns, wl.lam, wl.sigma, wl.tau, wl.n)
-    errs = [rel_l2(got[m], ref[m]) for m in range(M)]
-    print(f"small64 per-cycle rel L2: max {max(errs):.3e} mean {np.mean(errs):.3e}")
-    assert max(errs) <= REL_L2_PER_CYCLE
+    for m in range(M):
+        assert_cycle_parity(got[m], ref[m], f"small64 cycle {m}")
     # FP64 residual sums against the oracle's cycle residuals
     assert np.allclose(np.sqrt(sums[:, 1]), rh[0, :, 1], rtol=1e-6)
     r_gpu = np.sqrt(sums[:, 0])
@@ -69,11 +71,10 @@ def test_small64_full_run():
     st, hist = eed4.eed4_inpaint(u, to_dev(pr["mask"]), to_dev(pr["known"]),
                                  eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, wl.M), history=True)
     got = u.cpu().numpy()
-    e = rmse(got, ref)
-    print(f"small64 after {st.cycles} cycles: RMSE vs FP64 {e:.3e}, rel L2 {rel_l2(got, ref):.3e}; "
-          f"RMSE vs ground truth {rmse(got, pr['image']):.4f} (oracle {rmse(ref, pr['image']):.4f})")
+    print(f"small64 after {st.cycles} cycles: RMSE vs ground truth {rmse(got, pr['image']):.4f} "
+          f"(oracle {rmse(ref, pr['image']):.4f})")
     assert st.cycles == wl.M
-    assert e <= RMSE_STEADY
+    assert_steady_parity(got, ref, f"small64 after {st.cycles} cycles")
     assert np.array_equal(got[pr["mask"] != 0], pr["known"][pr["mask"] != 0])
     assert np.allclose(hist[:, 0, 1], rh[:, 1], rtol=1e-5)
 
@@ -95,9 +96,8 @@ def test_ragged_shapes_and_radii(H, W, sigma, lam, kernel):
     knowns = np.repeat(pr["known"][None], 2, 0)
     got, _ = gpu_cycle(ck, masks, knowns, lam, sigma, tau, n, KERNELS[kernel])
     ref, _ = oracle_cycle(ck, masks, knowns, lam, sigma, tau, n)
-    errs = [rel_l2(got[m], ref[m]) for m in range(2)]
-    print(f"{H}x{W} sigma {sigma} {kernel}: rel L2 {max(errs):.3e}")
-    assert max(errs) <= REL_L2_PER_CYCLE
+    for m in range(2):
+        assert_cycle_parity(got[m], ref[m], f"{H}x{W} sigma {sigma} {kernel} cycle {m}")
 
 
 @pytest.mark.parametrize("n", [1, 2, 3])
@@ -107,7 +107,7 @@ def test_short_cycles(n):
     st = pr["u_init"][None]
     got, _ = gpu_cycle(st, pr["mask"][None], pr["known"][None], 0.05, 1.0, 0.05, n)
     ref, _ = oracle_cycle(st, pr["mask"][None], pr["known"][None], 0.05, 1.0, 0.05, n)
-    assert rel_l2(got, ref) <= REL_L2_PER_CYCLE
+    assert_cycle_parity(got, ref, f"short cycle n={n}")
 
 
 def test_constant_image_is_stationary_bitwise():
@@ -161,34 +161,53 @@ def test_stop_rule_and_steady_state_512():
     print(f"single512: {st.cycles} cycles, final relative residual {st.rel_residual:.3e}")
     assert st.cycles < wl.M and st.rel_residual < wl.tol
     assert rel[-1] < wl.tol and np.all(rel[:-1] >= wl.tol)
-    ref, cyc, _ = oracle.inpaint(pr["u_init"], pr["mask"], pr["known"], wl.lam, wl.sigma,
-                                 wl.tau, wl.n, st.cycles)
-    e = rmse(got, ref)
-    print(f"single512 RMSE vs FP64 at {st.cycles} cycles: {e:.3e} (rel L2 {rel_l2(got, ref):.3e}); "
-          f"RMSE vs ground truth {rmse(got, pr['image']):.4f}")
-    assert e <= RMSE_STEADY
+    ref, cyc, oh = oracle.inpaint(pr["u_init"], pr["mask"], pr["known"], wl.lam, wl.sigma,
+                                  wl.tau, wl.n, st.cycles)
+    orel = oh[:, 0] / oh[:, 1]
+    gap = float(np.abs(rel / orel - 1).max())
+    print(f"single512: RMSE vs ground truth {rmse(got, pr['image']):.4f}; relative residuals "
+          f"within {gap:.2e} of FP64; oracle's last two {orel[-2]:.6e} {orel[-1]:.6e}")
+    assert_steady_parity(got, ref, f"single512 at {st.cycles} cycles")
+    # the FP64 run takes the same stop decision at every cycle: its residual history is
+    # within 1e-3 of the GPU's, and no cycle's residual lies that close to tol
+    assert gap <= 1e-3
+    assert np.all(np.abs(orel / wl.tol - 1) > 5 * gap)
+    assert orel[-1] < wl.tol and np.all(orel[:-1] >= wl.tol)
 
 
 def test_abs_tol_stop_rule_matches_oracle():
     # plain residual ||u^{m,n} - u^{m,0}||_2 < tol (EED4_ABS_TOL), as Sec. 3.3 states it
-    announce("absolute stop rule, 96x80, tol 1e-2")
     pr = make_problem(96, 80, 8, True, 0.01, 0.05, 808)
-    lam, sigma, tau, n, M, tol = 0.04, 1.5, 0.05, 10, 150, 1e-2
+    lam, sigma, tau, n, M = 0.04, 1.5, 0.05, 10, 150
+    # tol goes halfway (geometrically) between the FP64 residual of the first cycle below
+    # 1e-2 and the smallest one before it (consecutive cycles are about 3 % apart), so the
+    # FP32 path, whose residuals are within 2e-3 of FP64 (asserted), must stop at the same
+    # cycle as the oracle
+    _, _, oh = oracle.inpaint(pr["u_init"], pr["mask"], pr["known"], lam, sigma, tau, n, M)
+    ores = oh[:, 0]
+    c = int(np.argmax(ores < 1e-2))
+    assert 0 < c < M - 1 and ores[c] < ores[:c].min()
+    tol = float(np.sqrt(ores[c] * ores[:c].min()))
+    announce(f"absolute stop rule, 96x80, tol {tol:.6e} (oracle stops after cycle {c + 1})")
     u = to_dev(pr["u_init"])
     st, hist = eed4.eed4_inpaint(u, to_dev(pr["mask"]), to_dev(pr["known"]),
                                  eed4.params(lam, sigma, tau, n, M, tol=tol,
                                              flags=eed4.EED4_ABS_TOL), history=True)
     got = u.cpu().numpy()
     res = hist[:, 0, 0]
+    gap = float(np.abs(res / ores[:len(res)] - 1).max())
+    print(f"absolute stop: GPU {st.cycles} cycles (residual {st.residual:.4e}), oracle {c + 1}; "
+          f"residuals within {gap:.2e} of FP64")
+    assert gap <= 2e-3
+    assert st.cycles == c + 1
+    assert res[-1] < tol and np.all(res[:-1] >= tol)
+    assert st.residual == pytest.approx(res[-1], rel=1e-6)
     _, ocyc, _ = oracle.inpaint(pr["u_init"], pr["mask"], pr["known"], lam, sigma, tau, n, M,
                                 tol=tol, abs_tol=True)
-    print(f"absolute stop: GPU {st.cycles} cycles (residual {st.residual:.4e}), oracle {ocyc}")
-    assert st.cycles < M and res[-1] < tol and np.all(res[:-1] >= tol)
-    assert st.residual == pytest.approx(res[-1], rel=1e-6)
-    assert abs(st.cycles - ocyc) <= 1     # FP32 residual against FP64, 3 % apart per cycle
+    assert ocyc == c + 1
     ref, _, _ = oracle.inpaint(pr["u_init"], pr["mask"], pr["known"], lam, sigma, tau, n,
                                st.cycles)
-    assert rmse(got, ref) <= RMSE_STEADY
+    assert_steady_parity(got, ref, f"absolute stop at {st.cycles} cycles")
 
 
 @pytest.mark.parametrize("tol", [0.0, 1e-4])
@@ -287,9 +306,7 @@ def test_long_thin_images_one_cycle(shape, H, W):
     got, sums = gpu_cycle(u0[None], pr["mask"][None], pr["known"][None], 0.04, 1.5, 0.05, 6,
                           flags=eed4.EED4_FORCE_SHAPE(shape))
     ref, rh = oracle_cycle(u0[None], pr["mask"][None], pr["known"][None], 0.04, 1.5, 0.05, 6)
-    e = rel_l2(got[0], ref[0])
-    print(f"{H}x{W} {eed4.SHAPE_NAMES[shape]}: rel L2 {e:.3e}")
-    assert e <= REL_L2_PER_CYCLE
+    assert_cycle_parity(got[0], ref[0], f"{H}x{W} {eed4.SHAPE_NAMES[shape]}")
     assert np.allclose(np.sqrt(sums[0, 1]), rh[0, 0, 1], rtol=1e-6)
 
 
@@ -307,16 +324,12 @@ def test_large4096_first_cycle_parity():
                       eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, 1))
     tuned = eed4.eed4_step_shape(1, wl.H, wl.W, eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, 1))
     got_tuned = u.cpu().numpy()
-    e = rel_l2(got_tuned, ref[0])
-    print(f"large4096 first cycle, autotuned {eed4.SHAPE_NAMES[tuned]}: rel L2 {e:.3e}, "
-          f"max abs {np.abs(got_tuned - ref[0]).max():.3e}")
-    assert e <= REL_L2_PER_CYCLE
+    assert_cycle_parity(got_tuned, ref[0], f"large4096 first cycle, autotuned "
+                                           f"{eed4.SHAPE_NAMES[tuned]}")
     for shape in (3, 5):
         got, sums = gpu_cycle(u0[None], pr["mask"][None], pr["known"][None], wl.lam, wl.sigma,
                               wl.tau, wl.n, flags=eed4.EED4_FORCE_SHAPE(shape))
-        e = rel_l2(got[0], ref[0])
-        print(f"large4096 first cycle {eed4.SHAPE_NAMES[shape]}: rel L2 {e:.3e}")
-        assert e <= REL_L2_PER_CYCLE
+        assert_cycle_parity(got[0], ref[0], f"large4096 first cycle {eed4.SHAPE_NAMES[shape]}")
         assert np.allclose(np.sqrt(sums[0, 1]), rh[0, 0, 1], rtol=1e-6)
         if shape == tuned:
             assert np.array_equal(got[0], got_tuned)
@@ -331,7 +344,7 @@ def test_empty_mask_smoothing_case():
     st = pr["image"][None].astype(np.float32)
     got, _ = gpu_cycle(st, mask[None], st, 0.05, 1.0, 0.05, 10)
     ref, _ = oracle_cycle(st, mask[None], st, 0.05, 1.0, 0.05, 10)
-    assert rel_l2(got, ref) <= REL_L2_PER_CYCLE
+    assert_cycle_parity(got, ref, "empty mask")
     assert abs(float(got.astype(np.float64).mean()) - float(st.astype(np.float64).mean())) < 1e-6
 
 
