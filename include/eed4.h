@@ -69,7 +69,7 @@ extern "C" {
 #define EED4_NO_GRAPH        0x4
 /* Use the workgroup-tile step kernel (64 x 32 outputs per 256-thread
  * workgroup, stages separated by barriers) instead of the default wave-strip
- * kernel.  Both compute the same step; results agree to rounding. */
+ * kernel.  Both compute the same step with bitwise the same results. */
 #define EED4_TILE_KERNEL     0x8
 
 /* Use kernel shape s for the fused step instead of the automatic choice
@@ -80,7 +80,8 @@ extern "C" {
  * 60 columns x >= 64 rows, 4: strips of >= 136 rows, 5: strips of >= 28 rows,
  * 6: strips of >= 8 rows, 7: strips of 124 columns (two per lane) x >= 64 rows,
  * 8: 124-column strips of >= 28 rows, 9: 32x16 tiles, 10: 16x16 tiles.
- * All strip shapes give bitwise the same results; so do all tile shapes. */
+ * Every shape forms each value with the same operations in the same order, so
+ * all shapes give bitwise the same results. */
 #define EED4_FORCE_SHAPE(s)  ((((s) + 1) & 0xff) << 8)
 
 /* Tensor variants.  The default (both fields 0) is the paper's FOEED tensor:

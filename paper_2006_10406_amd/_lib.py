@@ -47,7 +47,7 @@ def EED4_MU3(r):
 
 SHAPE_NAMES = ("tile64x32", "tile64x16", "tile32x32", "strip", "strip_tall", "strip_short",
                "strip_tiny", "strip_wide", "strip_wide_short", "tile32x16", "tile16x16")
-# shape ids by kernel family (within a family every shape gives bitwise the same result)
+# shape ids by kernel family (every shape gives bitwise the same result)
 TILE_SHAPES = (0, 1, 2, 9, 10)
 STRIP_SHAPES = (3, 4, 5, 6, 7, 8)
 

@@ -248,8 +248,8 @@ std::string single_tune_key(int R, int B, int H, int W)
 // Fused step kernel of the single-image / equal-size-batch entry points:
 // EED4_FORCE_SHAPE, else EED4_TILE_KERNEL, else the autotuned choice for this
 // problem size, else tiles for problems too small for strips and strips
-// otherwise.  All strip shapes give bitwise the same result, as do all tile
-// shapes; strips and tiles agree to rounding.
+// otherwise.  All shapes give bitwise the same result (they share the
+// per-pixel arithmetic of eed4_pointwise.h), so the choice changes only speed.
 int step_shape(const eed4_params *p, int B, int H, int W)
 {
     if (model_of_flags(p->flags) != 0) return kShapeStripShort;   // the variant kernel

@@ -131,7 +131,7 @@ __global__ __launch_bounds__(256) void btile_kernel(const BImage *imgs, const BI
         step_tile<R, TW, TH>(smem, uni(pick(d, sc)), uni(pick(d, sp)), uni(pick(d, so)),
                              residual ? uni(d.buf[0]) : nullptr, uni(d.mask), uni(d.H), uni(d.W),
                              uni(t.iy), uni(t.ix), a.w, a.tau, a.alpha,
-                             __int_as_float(uni(__float_as_int(d.inv_lam2))),
+                             0.25f * __int_as_float(uni(__float_as_int(d.inv_lam2))),
                              residual ? partials + 2 * (size_t)uni(t.slot) : nullptr);
     }
 }

@@ -30,7 +30,7 @@ __global__ __launch_bounds__(256) void step_kernel(const float *ucur, const floa
     const int ty = t / nbx, tx = t - ty * nbx;
     const size_t off = (size_t)b * H * W;
     step_tile<R, TW, TH>(smem, ucur + off, uprev + off, uout + off, ref ? ref + off : nullptr,
-                         mask + off, H, W, ty, tx, a.w, a.tau, a.alpha, a.inv_lam2,
+                         mask + off, H, W, ty, tx, a.w, a.tau, a.alpha, 0.25f * a.inv_lam2,
                          partials ? partials + 2 * (size_t)tile : nullptr);
 }
 

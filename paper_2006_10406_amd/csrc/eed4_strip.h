@@ -22,6 +22,7 @@
 #pragma once
 
 #include "eed4_internal.h"
+#include "eed4_pointwise.h"
 
 namespace eed4 {
 
@@ -344,30 +345,18 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
                 const float *u0 = col + (q + R) * CS + (R - 1 + ph + D) % D;
                 const float *up = col + (q + R) * CS + (R + ph) % D;
                 uc[q] = u0[0];
-                const float hxx = fmaf(-2.0f, uc[q], u0[-CS] + u0[CS]);
-                const float hyy = fmaf(-2.0f, uc[q], um[0] + up[0]);
-                const float hxy = 0.25f * ((up[CS] + um[-CS]) - (up[-CS] + um[CS]));
+                const float hxx = second_diff(u0[-CS], uc[q], u0[CS]);
+                const float hyy = second_diff(um[0], uc[q], up[0]);
+                const float hxy = mixed_diff(up[CS], um[-CS], up[-CS], um[CS]);
 
-                const float s2 = fmaf(gxs, gxs, gys * gys);                  // 4 |grad|^2
+                const float s2 = grad2_sq(gxs, gys);                          // 4 |grad|^2
                 float mu1, mu3;
                 if constexpr (GEN) {
                     model_mu(s2 * s.il2q, s.model, mu1, mu3);
                 } else {                                     // FOEED: Charbonnier, sqrt
-                    mu1 = __builtin_amdgcn_rsqf(fmaf(s2, s.il2q, 1.0f));
-                    mu3 = __builtin_amdgcn_sqrtf(mu1);
+                    foeed_mu(s2, s.il2q, mu1, mu3);
                 }
-                const float rn = __builtin_amdgcn_rsqf(fmaxf(s2, 1e-30f));
-                const float nx = gxs * rn, ny = gys * rn;   // unit direction (0 where grad = 0)
-                const float aa = nx * nx, bb = ny * ny, c = nx * ny;
-                const float amb = aa - bb, c2 = c + c;
-                const float e1h = fmaf(aa, hxx, fmaf(bb, hyy, c2 * hxy));
-                const float x3 = fmaf(c, hyy - hxx, amb * hxy);
-                const float k1 = fmaf(mu1, e1h, -e1h);
-                const float k3 = fmaf(mu3, x3, -x3);
-                const float k3c2 = k3 * c2;
-                txx[q] = fmaf(k1, aa, hxx - k3c2);
-                tyy[q] = fmaf(k1, bb, hyy + k3c2);
-                txy[q] = fmaf(k1, c, fmaf(k3, amb, hxy));
+                contract(gxs, gys, s2, mu1, mu3, hxx, hyy, hxy, txx[q], tyy[q], txy[q]);
             }
 #pragma unroll
             for (int q = 0; q < CPL; ++q) {
@@ -385,11 +374,10 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
 #pragma unroll
                 for (int q = 0; q < CPL; ++q) {
                     const float sxx = left_of(txx_p, q) + right_of(txx_p, q);
-                    const float pu = fmaf(-2.0f, txx_p[q] + tyy_p[q], sxx + (tyy_pp[q] + tyy[q])) +
-                                     0.5f * (z[q] - z_pp[q]);
-                    const float wv = fmaf(-s.tau, pu, uc_p[q]);
-                    float un = fmaf(s.alpha, wv - cur.pv[q], cur.pv[q]);
-                    if (cur.mk[q]) un = uc_p[q];
+                    const float pu = outer_div(txx_p[q], tyy_p[q], sxx, tyy_pp[q] + tyy[q], z[q],
+                                               z_pp[q]);
+                    const float un = fsi_update(pu, uc_p[q], cur.pv[q], s.tau, s.alpha,
+                                                cur.mk[q] != 0);
                     if constexpr (RES) {
                         // columns without a pixel read 0 for the reference; add 0
                         const double du = out_col[q] ? (double)un : 0.0;

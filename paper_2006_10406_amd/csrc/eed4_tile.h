@@ -18,6 +18,7 @@
 #pragma once
 
 #include "eed4_internal.h"
+#include "eed4_pointwise.h"
 
 namespace eed4 {
 
@@ -27,33 +28,6 @@ __device__ __forceinline__ int mirror_index(int i, int n)
     int m = i % p;
     if (m < 0) m += p;
     return m < n ? m : p - 1 - m;
-}
-
-// T = H + (mu1 - 1)(E1:H) E1 + (mu3 - 1)(E3:H) E3 with n = grad/|grad|:
-// E1 = n n^T, E3 : H = sqrt2 [c (hyy - hxx) + (a - b) hxy],
-// (E3:H) E3 = [c (hyy-hxx) + (a-b) hxy] [[-2c, a-b], [a-b, 2c]],
-// a = nx^2, b = ny^2, c = nx ny.  mu2 = 1 and E4 : H = 0 drop out.
-__device__ __forceinline__ void contract_tensor(float gx, float gy, float inv_lam2, float hxx,
-                                                float hyy, float hxy, float &txx, float &tyy,
-                                                float &txy)
-{
-    float s2 = fmaf(gx, gx, gy * gy);
-    float mu1 = __builtin_amdgcn_rsqf(fmaf(s2, inv_lam2, 1.0f));
-    float mu3 = __builtin_amdgcn_sqrtf(mu1);
-    bool dir = s2 > 1e-30f;
-    float r = __builtin_amdgcn_rsqf(dir ? s2 : 1.0f);
-    float nx = dir ? gx * r : 1.0f;
-    float ny = dir ? gy * r : 0.0f;
-    float a = nx * nx, b = ny * ny, c = nx * ny;
-    float amb = a - b;
-    float e1h = fmaf(a, hxx, fmaf(b, hyy, 2.0f * c * hxy));
-    float x3 = fmaf(c, hyy - hxx, amb * hxy);
-    float k1 = (mu1 - 1.0f) * e1h;
-    float k3 = (mu3 - 1.0f) * x3;
-    float k3c = 2.0f * k3 * c;
-    txx = fmaf(k1, a, hxx - k3c);
-    tyy = fmaf(k1, b, hyy + k3c);
-    txy = fmaf(k1, c, fmaf(k3, amb, hxy));
 }
 
 template <int R, int TW, int TH>
@@ -120,7 +94,7 @@ __device__ __forceinline__ void step_tile(float *smem, const float *ucur, const 
                                           float *uout, const float *ref,
                                           const uint8_t *__restrict__ mask, int H, int W, int ty,
                                           int tx, const float (&w)[2 * kRMax + 1], float tau,
-                                          float alpha, float inv_lam2, double *partial)
+                                          float alpha, float il2q, double *partial)
 {
     using G = TileGeo<R, TW, TH>;
     float *sU = smem;
@@ -227,14 +201,17 @@ __device__ __forceinline__ void step_tile(float *smem, const float *ucur, const 
         if (p < G::NP) {
             int pr = p / G::PW, pc = p - pr * G::PW;
             const float *v = sV + (pr + 1) * G::XW + (pc + 1);
-            float gx = 0.5f * (v[1] - v[-1]);
-            float gy = 0.5f * (v[G::XW] - v[-G::XW]);
+            const float gxs = v[1] - v[-1];                          // 2 gx
+            const float gys = v[G::XW] - v[-G::XW];                  // 2 gy
             const float *u = sU + (pr + G::h - 1) * G::UW + (pc + G::h - 1);
-            float uc = u[0];
-            float hxx = (u[-1] - uc) + (u[1] - uc);
-            float hyy = (u[-G::UW] - uc) + (u[G::UW] - uc);
-            float hxy = 0.25f * ((u[G::UW + 1] + u[-G::UW - 1]) - (u[G::UW - 1] + u[-G::UW + 1]));
-            contract_tensor(gx, gy, inv_lam2, hxx, hyy, hxy, txx[k], tyy[k], txy[k]);
+            const float uc = u[0];
+            const float hxx = second_diff(u[-1], uc, u[1]);
+            const float hyy = second_diff(u[-G::UW], uc, u[G::UW]);
+            const float hxy = mixed_diff(u[G::UW + 1], u[-G::UW - 1], u[G::UW - 1], u[-G::UW + 1]);
+            const float s2 = grad2_sq(gxs, gys);                     // 4 |grad|^2
+            float mu1, mu3;
+            foeed_mu(s2, il2q, mu1, mu3);
+            contract(gxs, gys, s2, mu1, mu3, hxx, hyy, hxy, txx[k], tyy[k], txy[k]);
         }
     }
     __syncthreads();
@@ -261,15 +238,13 @@ __device__ __forceinline__ void step_tile(float *smem, const float *ucur, const 
             const float *Txx = sT + p;
             const float *Tyy = sT + G::NP + p;
             const float *Txy = sT + 2 * G::NP + p;
-            float pu = ((Txx[-1] - Txx[0]) + (Txx[1] - Txx[0])) +
-                       ((Tyy[-G::PW] - Tyy[0]) + (Tyy[G::PW] - Tyy[0])) +
-                       0.5f * ((Txy[G::PW + 1] + Txy[-G::PW - 1]) - (Txy[G::PW - 1] + Txy[-G::PW + 1]));
+            const float pu = outer_div(Txx[0], Tyy[0], Txx[-1] + Txx[1], Tyy[-G::PW] + Tyy[G::PW],
+                                       Txy[G::PW + 1] - Txy[G::PW - 1],
+                                       Txy[-G::PW + 1] - Txy[-G::PW - 1]);
             size_t gi = (size_t)gy * W + gx;
-            float uk = PF ? ek[e] : ucur[gi];
-            float up = PF ? ep[e] : uprev[gi];
-            float wv = fmaf(-tau, pu, uk);
-            float un = fmaf(alpha, wv - up, up);
-            if (PF ? em[e] : mask[gi]) un = uk;
+            const float uk = PF ? ek[e] : ucur[gi];
+            const float up = PF ? ep[e] : uprev[gi];
+            const float un = fsi_update(pu, uk, up, tau, alpha, (PF ? em[e] : mask[gi]) != 0);
             if (ref) {
                 double dd = (double)un - (double)(PF ? ef[e] : ref[gi]);
                 d2 = fma(dd, dd, d2);

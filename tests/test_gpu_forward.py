@@ -12,8 +12,7 @@ import pytest
 
 import oracle
 from synth import WORKLOADS, make_batch, make_problem
-from tests.helpers import (announce, assert_cycle_parity, assert_steady_parity, rel_l2, rmse,
-                           to_dev)
+from tests.helpers import announce, assert_cycle_parity, assert_steady_parity, rmse, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -261,7 +260,9 @@ def test_concurrent_host_threads():
             assert np.array_equal(outs[i].cpu().numpy(), ref[i])
 
 
-def test_strip_and_tile_kernels_agree():
+def test_strip_and_tile_kernels_agree_bitwise():
+    # both kernel families form every value with the same operations in the same order, so
+    # the result does not depend on which shape the autotuner picks
     announce("strip vs tile kernel, 300x260, 3 cycles")
     pr = make_problem(300, 260, 12, True, 0.01, 0.04, 555)
     outs = []
@@ -270,9 +271,7 @@ def test_strip_and_tile_kernels_agree():
         eed4.eed4_inpaint(u, to_dev(pr["mask"]), to_dev(pr["known"]),
                           eed4.params(0.03, 1.5, 0.05, 15, 3, flags=f))
         outs.append(u.cpu().numpy())
-    e = rel_l2(outs[0], outs[1])
-    print(f"strip vs tile rel L2 {e:.3e}")
-    assert e <= 1e-6
+    assert np.array_equal(outs[0], outs[1])
 
 
 @pytest.mark.parametrize("H,W,B", [(300, 260, 1), (96, 80, 4)])
@@ -287,12 +286,9 @@ def test_every_step_shape_and_the_autotuned_default(H, W, B):
         eed4.eed4_inpaint(u, to_dev(b["mask"]), to_dev(b["known"]),
                           eed4.params(0.03, 1.5, 0.05, 9, 2, flags=flags))
         outs[shape] = u.cpu().numpy()
-    for sh in eed4.TILE_SHAPES:
-        assert np.array_equal(outs[sh], outs[0])       # tile shapes: same arithmetic
-    for sh in eed4.STRIP_SHAPES:
-        assert np.array_equal(outs[sh], outs[3])       # strip heights: same arithmetic
-    assert rel_l2(outs[3], outs[0]) <= 1e-6
-    assert np.array_equal(outs[None], outs[0]) or np.array_equal(outs[None], outs[3])
+    for sh in range(len(eed4.SHAPE_NAMES)):
+        assert np.array_equal(outs[sh], outs[0]), eed4.SHAPE_NAMES[sh]   # same arithmetic
+    assert np.array_equal(outs[None], outs[0])
 
 
 @pytest.mark.parametrize("shape", [2, 3, 5, 7])
