@@ -4,7 +4,10 @@
 // Each kernel gathers the neighbours its own way (LDS ring, DPP lane shifts,
 // LDS tiles), but every value is formed by these functions with the same
 // operands in the same order, so all kernel shapes give bitwise the same
-// result for every pixel.
+// result for every pixel.  Floating-point contraction is switched off inside
+// them and every fused multiply-add is written out: otherwise the compiler
+// fuses a product into a neighbouring add in one kernel and not in another,
+// depending on how the surrounding code is laid out, and the roundings differ.
 #pragma once
 
 #include "eed4_internal.h"
@@ -15,6 +18,7 @@ namespace eed4 {
 // one axis.
 __device__ __forceinline__ float second_diff(float a, float c, float b)
 {
+#pragma clang fp contract(off)
     return fmaf(-2.0f, c, a + b);
 }
 
@@ -23,6 +27,7 @@ __device__ __forceinline__ float second_diff(float a, float c, float b)
 // mp = u(y-1, x+1).
 __device__ __forceinline__ float mixed_diff(float pp, float mm, float pm, float mp)
 {
+#pragma clang fp contract(off)
     return 0.25f * ((pp + mm) - (pm + mp));
 }
 
@@ -31,6 +36,7 @@ __device__ __forceinline__ float mixed_diff(float pp, float mm, float pm, float 
 // (2 grad u_sigma, Sec. 3.1).
 __device__ __forceinline__ float grad2_sq(float gxs, float gys)
 {
+#pragma clang fp contract(off)
     return fmaf(gxs, gxs, gys * gys);
 }
 
@@ -39,6 +45,7 @@ __device__ __forceinline__ float grad2_sq(float gxs, float gys)
 // mu3 = sqrt(mu1 mu2).
 __device__ __forceinline__ void foeed_mu(float s2, float il2q, float &mu1, float &mu3)
 {
+#pragma clang fp contract(off)
     mu1 = __builtin_amdgcn_rsqf(fmaf(s2, il2q, 1.0f));
     mu3 = __builtin_amdgcn_sqrtf(mu1);
 }
@@ -54,6 +61,7 @@ __device__ __forceinline__ void contract(float gxs, float gys, float s2, float m
                                          float hxx, float hyy, float hxy, float &txx, float &tyy,
                                          float &txy)
 {
+#pragma clang fp contract(off)
     const float rn = __builtin_amdgcn_rsqf(fmaxf(s2, 1e-30f));
     const float nx = gxs * rn, ny = gys * rn;
     const float aa = nx * nx, bb = ny * ny, c = nx * ny;
@@ -76,7 +84,8 @@ __device__ __forceinline__ void contract(float gxs, float gys, float s2, float m
 __device__ __forceinline__ float outer_div(float txx_c, float tyy_c, float sxx, float syy,
                                            float zd, float zu)
 {
-    return fmaf(-2.0f, txx_c + tyy_c, sxx + syy) + 0.5f * (zd - zu);
+#pragma clang fp contract(off)
+    return fmaf(0.5f, zd - zu, fmaf(-2.0f, txx_c + tyy_c, sxx + syy));
 }
 
 // Explicit step and FSI extrapolation (Sec. 3.3),
@@ -85,6 +94,7 @@ __device__ __forceinline__ float outer_div(float txx_c, float tyy_c, float sxx, 
 __device__ __forceinline__ float fsi_update(float pu, float uk, float uprev, float tau,
                                             float alpha, bool known)
 {
+#pragma clang fp contract(off)
     const float wv = fmaf(-tau, pu, uk);
     const float un = fmaf(alpha, wv - uprev, uprev);
     return known ? uk : un;

@@ -103,6 +103,7 @@ struct StripArgs {
 // mu2 = 1).  model = diffusivity | rule << 4, uniform over the launch.
 __device__ __forceinline__ void model_mu(float x, int model, float &mu1, float &mu3)
 {
+#pragma clang fp contract(off)
     const int diff = model & 0xf, rule = model >> 4;
     const float d = 1.0f + x;
     float g;
