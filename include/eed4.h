@@ -55,6 +55,8 @@ extern "C" {
 #define EED4_EWORKSPACE (-3)  /* workspace missing, misaligned or too small  */
 #define EED4_EHIP       (-4)  /* a HIP runtime call or kernel launch failed  */
 #define EED4_EDIVERGED  (-5)  /* non-finite cycle residual                   */
+#define EED4_ETOOLARGE  (-6)  /* problem needs more than the static scratch of
+                                 eed4_fsi_cycle_static                       */
 
 /* ---- flags (eed4_params.flags) ---- */
 /* Accept tau > 1/16.  The explicit step is L2-stable for tau <= 1/16 because
@@ -181,6 +183,28 @@ int eed4_inpaint(float *u, const uint8_t *mask, const float *known,
 int eed4_fsi_cycle(float *u, const uint8_t *mask, const float *known,
                    int B, int H, int W, const eed4_params *p,
                    void *ws, size_t ws_bytes, void *stream, double *d_sums);
+
+/* Bytes of the static device scratch of eed4_fsi_cycle_static (per device). */
+#define EED4_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* eed4_fsi_cycle without a workspace, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  The cycle's scratch (the two rotation buffers and the
+ * residual partials) lives in a static device array of
+ * EED4_STATIC_SCRATCH_BYTES that every device the library runs on holds until
+ * the process ends; the call itself allocates nothing.  Arguments, results and
+ * errors are those of eed4_fsi_cycle, and so are the results, bitwise.
+ * Limit: a problem fits when eed4_workspace_size(EED4_OP_CYCLE, B, H, W, p)
+ * <= EED4_STATIC_SCRATCH_BYTES (B*H*W up to about 8 million pixels, e.g. one
+ * 2048 x 2048 image or 16 images of 512 x 512); larger ones return
+ * EED4_ETOOLARGE before any device work.  Every call on one device shares that
+ * device's scratch: calls that overlap on one device (two host threads, or
+ * two streams with no ordering between them) race and give undefined results.
+ * The first call on a device looks up the array's address there (no
+ * allocation); nothing in the scratch needs clearing between calls. */
+int eed4_fsi_cycle_static(float *u, const uint8_t *mask, const float *known,
+                          int B, int H, int W, const eed4_params *p,
+                          void *stream, double *d_sums);
 
 /* One FSI inner step (Sec. 3.3) of B equal-size images:
  *   uout = alpha_k (I - tau P(ucur)) ucur + (1 - alpha_k) uprev,

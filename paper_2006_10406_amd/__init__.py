@@ -32,7 +32,7 @@ _lib.lib()  # fail loudly at import if libeed4.so is missing
 
 __all__ = [
     "EED4Error", "params", "eed4_radius", "eed4_workspace_size", "eed4_inpaint",
-    "eed4_fsi_cycle", "eed4_fsi_step", "eed4_backward", "eed4_batched_workspace_size", "eed4_inpaint_batched",
+    "eed4_fsi_cycle", "eed4_fsi_cycle_static", "eed4_fsi_step", "eed4_backward", "eed4_batched_workspace_size", "eed4_inpaint_batched",
     "eed4_strerror", "EED4_ABS_TOL", "EED4_ALLOW_LARGE_TAU", "EED4_NO_GRAPH", "EED4_TILE_KERNEL",
     "EED4_OP_INPAINT", "EED4_OP_CYCLE", "EED4_OP_BACKWARD", "EED4_FORCE_SHAPE", "SHAPE_NAMES", "TILE_SHAPES", "STRIP_SHAPES",
     "eed4_autotune_batched", "eed4_step_shape", "library_path",
@@ -166,6 +166,23 @@ def eed4_fsi_cycle(u: torch.Tensor, mask: torch.Tensor, known: torch.Tensor, p: 
     rc = _lib.lib().eed4_fsi_cycle(u.data_ptr(), mask.data_ptr(), known.data_ptr(), B, H, W,
                                    ctypes.byref(p), wp, wsz, _stream(u, stream), d_sums.data_ptr())
     _check(rc, "eed4_fsi_cycle")
+
+
+def eed4_fsi_cycle_static(u: torch.Tensor, mask: torch.Tensor, known: torch.Tensor,
+                          p: eed4_params, d_sums: torch.Tensor, stream=None):
+    """eed4_fsi_cycle with the library's static device scratch instead of a workspace:
+    allocates nothing (not even through torch).  Problems whose cycle workspace exceeds
+    EED4_STATIC_SCRATCH_BYTES raise EED4Error(EED4_ETOOLARGE)."""
+    _dev_tensor(u, torch.float32, "u")
+    B, H, W = _bhw(u, "u")
+    _mask_known(u, mask, known, B, H, W)
+    _dev_tensor(d_sums, torch.float64, "d_sums")
+    if d_sums.numel() < 2 * B:
+        raise ValueError("d_sums must hold 2*B doubles")
+    rc = _lib.lib().eed4_fsi_cycle_static(u.data_ptr(), mask.data_ptr(), known.data_ptr(), B, H,
+                                          W, ctypes.byref(p), _stream(u, stream),
+                                          d_sums.data_ptr())
+    _check(rc, "eed4_fsi_cycle_static")
 
 
 def eed4_fsi_step(ucur: torch.Tensor, uprev: torch.Tensor, uout: torch.Tensor,

@@ -14,6 +14,8 @@ EED4_EUNSTABLE = -2
 EED4_EWORKSPACE = -3
 EED4_EHIP = -4
 EED4_EDIVERGED = -5
+EED4_ETOOLARGE = -6
+EED4_STATIC_SCRATCH_BYTES = 64 << 20
 
 EED4_ALLOW_LARGE_TAU = 0x1
 EED4_ABS_TOL = 0x2
@@ -56,7 +58,7 @@ EED4_OP_CYCLE = 2
 EED4_OP_BACKWARD = 3
 
 EXPORTED = ("eed4_radius", "eed4_workspace_size", "eed4_inpaint", "eed4_fsi_cycle",
-            "eed4_fsi_step",
+            "eed4_fsi_cycle_static", "eed4_fsi_step",
             "eed4_backward", "eed4_batched_workspace_size", "eed4_inpaint_batched",
             "eed4_autotune_batched", "eed4_step_shape", "eed4_strerror")
 
@@ -98,6 +100,8 @@ def lib():
                                    ctypes.POINTER(eed4_stats), vp]
         L.eed4_fsi_cycle.restype = i
         L.eed4_fsi_cycle.argtypes = [vp, vp, vp, i, i, i, pp, vp, sz, vp, vp]
+        L.eed4_fsi_cycle_static.restype = i
+        L.eed4_fsi_cycle_static.argtypes = [vp, vp, vp, i, i, i, pp, vp, vp]
         L.eed4_fsi_step.restype = i
         L.eed4_fsi_step.argtypes = [vp, vp, vp, vp, i, i, i, pp, i, vp]
         L.eed4_backward.restype = i

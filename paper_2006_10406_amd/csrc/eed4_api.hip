@@ -292,6 +292,37 @@ int check_ws(void *ws, size_t ws_bytes, size_t need)
     return EED4_OK;
 }
 
+// ---- static scratch of the allocation-free entry point ----
+// In host code `scratch` is only a host-side stand-in for the device array:
+// kernels and copies get the device address that hipGetSymbolAddress returns
+// on each device (every device holds its own copy, at its own address).
+static __device__ __align__(256) unsigned char scratch[EED4_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on the current device, looked up on the first
+// call per device and kept.
+static int static_scratch(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "static scratch: hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return hip_fail(hipErrorInvalidDevice, "static scratch");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "static scratch: hipGetSymbolAddress");
+        if (!ptr || ((uintptr_t)ptr & 255) != 0)
+            return hip_fail(hipErrorInvalidSymbol, "static scratch: address");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return EED4_OK;
+}
+
 }  // namespace eed4
 
 using namespace eed4;
@@ -431,6 +462,21 @@ int eed4_fsi_cycle(float *u, const uint8_t *mask, const float *known, int B, int
     return enqueue_cycle(j, s);
 }
 
+int eed4_fsi_cycle_static(float *u, const uint8_t *mask, const float *known, int B, int H,
+                          int W, const eed4_params *p, void *stream, double *d_sums)
+{
+    int rc = check_params(p, B, H, W);
+    if (rc != EED4_OK) return rc;
+    if (!u || !mask || !known || !d_sums) return EED4_EINVAL;
+    const size_t need =
+        inpaint_layout(EED4_OP_CYCLE, B, H, W, eed4_radius(p->sigma), 1).total;
+    if (need > EED4_STATIC_SCRATCH_BYTES) return EED4_ETOOLARGE;
+    void *ws = nullptr;
+    if ((rc = static_scratch(&ws)) != EED4_OK) return rc;
+    return eed4_fsi_cycle(u, mask, known, B, H, W, p, ws, EED4_STATIC_SCRATCH_BYTES, stream,
+                          d_sums);
+}
+
 int eed4_fsi_step(const float *ucur, const float *uprev, float *uout, const uint8_t *mask,
                   int B, int H, int W, const eed4_params *p, int k, void *stream)
 {
@@ -461,6 +507,9 @@ const char *eed4_strerror(int code)
         return msg.c_str();
     }
     case EED4_EDIVERGED: return "non-finite cycle residual (diverged)";
+    case EED4_ETOOLARGE:
+        return "problem larger than the static scratch of eed4_fsi_cycle_static "
+               "(EED4_STATIC_SCRATCH_BYTES)";
     default: return "unknown error code";
     }
 }

@@ -156,3 +156,22 @@ def test_strerror(lib):
     import paper_2006_10406_amd as e
     for c in (0, -1, -2, -3, -4, -5, 7):
         assert isinstance(e.eed4_strerror(c), str) and e.eed4_strerror(c)
+
+
+def test_static_cycle_size_limit_before_any_gpu_work(lib):
+    # eed4_fsi_cycle_static rejects a problem whose cycle workspace exceeds its static
+    # scratch with EED4_ETOOLARGE before touching the device (dummy pointers here)
+    import paper_2006_10406_amd as e
+    p = e.params(0.03, 1.5, 0.05, 10, 1)
+    limit = e._lib.EED4_STATIC_SCRATCH_BYTES
+    assert e.eed4_workspace_size(e.EED4_OP_CYCLE, 1, 3000, 3000, p) > limit
+    assert e.eed4_workspace_size(e.EED4_OP_CYCLE, 1, 2048, 2048, p) <= limit
+    ptr = 0x2000
+    rc = lib.eed4_fsi_cycle_static(ptr, ptr, ptr, 1, 3000, 3000, ctypes.byref(p), None, ptr)
+    assert rc == e._lib.EED4_ETOOLARGE
+    assert b"static scratch" in lib.eed4_strerror(rc)
+    bad = e.params(-1.0, 1.5, 0.05, 10, 1)
+    assert lib.eed4_fsi_cycle_static(ptr, ptr, ptr, 1, 8, 8, ctypes.byref(bad), None,
+                                     ptr) == e._lib.EED4_EINVAL
+    assert lib.eed4_fsi_cycle_static(ptr, ptr, ptr, 1, 8, 8, ctypes.byref(p), None,
+                                     None) == e._lib.EED4_EINVAL
