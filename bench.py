@@ -14,13 +14,23 @@ The JSON line carries:
              events around back-to-back eed4_fsi_step launches on the same
              stream, against the 8 TB/s HBM peak; traffic from the committed
              rocprofv3 counter summary when it matches the current kernel
-  cpu_baseline  the FP64 oracle on the host cores, one cycle of the same image
+  roofline.out_of_cache  the same fused step on an 8192 x 8192 image, whose
+             832 MiB working set cannot stay in the 256 MB Infinity Cache
+  cpu_baseline  the FP64 oracle on the host cores, one cycle of the same image;
+             beside it a single-thread sample and the oracle rate on the
+             other workloads (64^2, 512^2, 16 x 256^2, part of the uneven batch)
+  fp64_error  the FP32 GPU result against the FP64 oracle for every reported
+             result (relative L2, largest elementwise error, RMSE): the first
+             cycle of the timed image here, and one object inside each of the
+             objects below
   adjoint_forward_ratio  backward/forward time on 16 x 256 x 256 (30 cycles of 10)
   batched    64 uneven images: one batched call vs 64 single-image calls
   variants   fused step time of each tensor variant (Table 7 diffusivities,
              Sec. 3.1 mu3 choices) on the workload image
   workloads  colour (channel-wise RGB) and scratch-removal inpainting, 512x512,
              and the 512x512 single image run to its relative-residual tolerance
+The oracle runs behind every fp64_error object are done after all GPU
+timing, so the host work does not let the GPU clock drop between timings.
 """
 import argparse
 import hashlib
@@ -91,17 +101,93 @@ def measured_traffic(kname):
     return t.get("kernels", {}).get(kname, {}).get("bytes_per_launch")
 
 
-def cpu_baseline(pr, wl):
-    import oracle
-    n = wl.n
+def fp64_error(got, ref):
+    """FP32 result against the FP64 oracle: relative L2, largest elementwise error, RMSE."""
+    import numpy as np
+    a = np.asarray(got, np.float64)
+    b = np.asarray(ref, np.float64)
+    d = a - b
+    return {"rel_l2": float(np.linalg.norm(d) / max(np.linalg.norm(b), 1e-300)),
+            "max_abs": float(np.abs(d).max()) if d.size else 0.0,
+            "rmse": float(np.sqrt(np.mean(d * d))) if d.size else 0.0}
+
+
+def grad_error(got, ref):
+    """A gradient against the oracle adjoint: relative L2 and the largest elementwise error
+    relative to the largest oracle value."""
+    import numpy as np
+    a = np.asarray(got, np.float64)
+    b = np.asarray(ref, np.float64)
+    scale = float(np.abs(b).max()) if b.size else 0.0
+    return {"rel_l2": float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)),
+            "max_abs_rel": float(np.abs(a - b).max() / scale) if scale > 0 else 0.0}
+
+
+def timed_oracle(fn, updates):
+    """Runs fn() once; returns (Mpixel-updates/s, seconds, result)."""
     t0 = time.perf_counter()
-    oracle.inpaint(pr["u_init"], pr["mask"], pr["known"], wl.lam, wl.sigma, wl.tau, n, 1)
+    res = fn()
     dt = time.perf_counter() - t0
-    upd = pr["u_init"].size * n
-    return {"value": upd / dt / 1e6, "unit": "Mpixel-updates/s", "cores": oracle.num_threads(),
-            "kind": "oracle", "cpu": cpu_model(),
-            "sample": f"one FSI cycle ({n} steps) of the full {wl.H}x{wl.W} workload image, "
-                      f"FP64, {dt:.1f} s"}
+    return updates / dt / 1e6, dt, res
+
+
+def cpu_baseline(pr, wl):
+    """The FP64 oracle on the host: one cycle of the timed image on every core (the
+    reported value), a single-thread sample of it, and the rate on the other workloads.
+    Returns (cpu_baseline object, the oracle's first cycle of the timed image)."""
+    import oracle
+    from synth import WORKLOADS, make_batch, make_problem, make_uneven_batch
+    n = wl.n
+    cores = oracle.num_threads()
+    one_cycle = lambda p, w, M=1: (lambda: oracle.inpaint(p["u_init"], p["mask"], p["known"],
+                                                          w.lam, w.sigma, w.tau, w.n, M)[0])
+    val, dt, first = timed_oracle(one_cycle(pr, wl), pr["u_init"].size * n)
+    out = {"value": val, "unit": "Mpixel-updates/s", "cores": cores, "kind": "oracle",
+           "cpu": cpu_model(),
+           "sample": f"one FSI cycle ({n} steps) of the full {wl.H}x{wl.W} workload image, "
+                     f"FP64, {dt:.1f} s"}
+    # single thread: rows 0..511 of the same image, one cycle (a cycle of a row band costs
+    # what the same rows cost inside the full image, up to the mirrored border rows)
+    band = {k: pr[k][:512] for k in ("u_init", "mask", "known")}
+    oracle.set_num_threads(1)
+    try:
+        v1, d1, _ = timed_oracle(one_cycle(band, wl), band["u_init"].size * n)
+        per = {}
+        # the other workloads, each at 1 thread and on every core: 64^2 whole (20 cycles of
+        # 10), 512^2 one cycle of 40, 16 x 256^2 one cycle of 10, and 4 images of the uneven
+        # batch (one cycle of 15)
+        w1 = WORKLOADS["small64"]
+        p1 = make_problem(w1.H, w1.W, w1.n_ellipses, w1.ramp, w1.noise_std, w1.density,
+                          w1.seed_base)
+        w2 = WORKLOADS["single512"]
+        p2 = make_problem(w2.H, w2.W, w2.n_ellipses, w2.ramp, w2.noise_std, w2.density,
+                          w2.seed_base)
+        w5 = WORKLOADS["adjoint16"]
+        p5 = make_batch(w5)
+        w4 = WORKLOADS["batch64"]
+        p4 = make_uneven_batch(w4)[:4]
+        cases = [("small64", w1, [p1], w1.M, f"{w1.M} cycles of {w1.n}, 64x64"),
+                 ("single512", w2, [p2], 1, f"one cycle of {w2.n}, 512x512"),
+                 ("adjoint16", w5, [p5], 1, f"one cycle of {w5.n}, 16 x 256x256"),
+                 ("batch64", w4, p4, 1, "one cycle of 15 on images 0-3 of the uneven batch")]
+        for name, w, probs, M, what in cases:
+            upd = sum(q["u_init"].size for q in probs) * w.n * M
+            rates = {}
+            for nt in (1, cores):
+                oracle.set_num_threads(nt)
+                t0 = time.perf_counter()
+                for q in probs:
+                    one_cycle(q, w, M)()
+                rates[nt] = upd / (time.perf_counter() - t0) / 1e6
+            per[name] = {"single_thread": round(rates[1], 2), "all_cores": round(rates[cores], 2),
+                         "sample": what}
+    finally:
+        oracle.set_num_threads(cores)
+    out["single_thread"] = {"value": round(v1, 2), "cores": 1,
+                            "sample": f"one FSI cycle of rows 0-511 of the {wl.H}x{wl.W} image, "
+                                      f"{d1:.1f} s"}
+    out["per_workload"] = per
+    return out, first
 
 
 def cpu_model():
@@ -186,9 +272,30 @@ def adjoint_ratio(eed4, torch, args):
     tf = timed(fwd, 3)
     tb = timed(bwd, 3)
     upd = B * H * W * wl.n * wl.M
-    return {"forward_ms": tf, "backward_ms": tb, "ratio": tb / tf,
-            "forward_mpix_updates_s": upd / (tf * 1e-3) / 1e6,
-            "workload": f"adjoint16: {B} x {H}x{W}, {wl.M} cycles of {wl.n}, checkpoint per cycle"}
+    res = {"forward_ms": tf, "backward_ms": tb, "ratio": tb / tf,
+           "forward_mpix_updates_s": upd / (tf * 1e-3) / 1e6,
+           "workload": f"adjoint16: {B} x {H}x{W}, {wl.M} cycles of {wl.n}, checkpoint per cycle"}
+    # image 0 for the FP64 check: forward state after M cycles and the three gradients
+    i0 = {"u": u[0].cpu().numpy(), "ck": ck[:, 0].cpu().numpy(), "gu": gu[0].cpu().numpy(),
+          "gk": gk[0].cpu().numpy(), "gi": gi[0].cpu().numpy(), "gl": float(gl[0])}
+
+    def check():
+        import numpy as np
+        import oracle
+        pr = {k: b[k][0] for k in ("u_init", "mask", "known")}
+        ref, _, _ = oracle.inpaint(pr["u_init"], pr["mask"], pr["known"], wl.lam, wl.sigma,
+                                   wl.tau, wl.n, wl.M)
+        ogk, ogi, ogl = oracle.backward(i0["ck"].astype(np.float64), pr["mask"], pr["known"],
+                                        wl.lam, wl.sigma, wl.tau, wl.n, i0["gu"])
+        m = pr["mask"] != 0
+        return {"image": 0, "forward_after_30_cycles": fp64_error(i0["u"], ref),
+                "dL_df": grad_error(i0["gk"][m], ogk[m]),
+                "dL_du_init": grad_error(i0["gi"][~m], ogi[~m]),
+                "dL_dlambda": {"gpu": i0["gl"], "oracle": float(ogl),
+                               "rel": abs(i0["gl"] - float(ogl)) / max(abs(float(ogl)), 1e-300)},
+                "reference": "FP64 oracle forward from the same input; oracle adjoint on the "
+                             "GPU's own checkpoints"}
+    return res, check
 
 
 def probe(eed4, torch, u_init, mask, wl):
@@ -262,12 +369,34 @@ def variants_timing(eed4, torch, u, mask, wl, stream, reps=2):
     return res
 
 
+def variant_first_cycle(eed4, torch, pr, mask, known, wl, d=2, r=1):
+    """One variant's (default: exponential Perona-Malik, arithmetic-mean mu3) first cycle of
+    the workload image on the GPU, and the deferred FP64 check of it."""
+    u = torch.from_numpy(pr["u_init"]).cuda()
+    sums = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
+    eed4.eed4_fsi_cycle(u, mask, known, eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, 1,
+                                                    flags=eed4.EED4_DIFFUSIVITY(d)
+                                                    | eed4.EED4_MU3(r)), sums)
+    got = u.cpu().numpy()
+
+    def check():
+        import oracle
+        ref, _, _ = oracle.inpaint(pr["u_init"], pr["mask"], pr["known"], wl.lam, wl.sigma,
+                                   wl.tau, wl.n, 1, diff=d, mu3=r)
+        e = fp64_error(got, ref)
+        e["variant"] = f"{eed4.DIFFUSIVITY_NAMES[d]}/{eed4.MU3_NAMES[r]}"
+        e["sample"] = f"first FSI cycle of the {wl.H}x{wl.W} workload image"
+        return e
+    return check
+
+
 def workload_throughput(eed4, torch, names=("rgb512", "scratch512_thin", "scratch512_thick")):
     """Colour (channel-wise, a batch of 3 planes) and scratch-removal workloads through
     eed4_inpaint: wl.M fixed cycles after a tuning call; pixel-updates/s counts every
     channel's pixels."""
     from synth import WORKLOADS, make_problem, make_workload_problem
     res = {}
+    checks = []
     for name in names:
         wl = WORKLOADS[name]
         pr = make_workload_problem(wl)
@@ -291,6 +420,12 @@ def workload_throughput(eed4, torch, names=("rgb512", "scratch512_thin", "scratc
         res[name] = {"mpix_updates_s": round(px * wl.n * st.cycles / (ms * 1e-3) / 1e6, 1),
                      "ms": round(ms, 3), "cycles": st.cycles, "planes": B,
                      "shape": eed4.SHAPE_NAMES[eed4.eed4_step_shape(B, wl.H, wl.W, p)]}
+        # the colour planes are independent: channel 0 stands for the three
+        got = u.cpu().numpy()
+        got, q = (got[0], {k: pr[k][0] for k in ("u_init", "mask", "known")}) if B > 1 \
+            else (got, pr)
+        checks.append((name, deferred_run(got, q, wl, st.cycles,
+                                          "channel 0" if B > 1 else "the image")))
     # the 512x512 single image run to the relative-residual tolerance (one host read of the
     # residual per cycle): time to convergence
     wl = WORKLOADS["single512"]
@@ -312,7 +447,22 @@ def workload_throughput(eed4, torch, names=("rgb512", "scratch512_thin", "scratc
                                "mpix_updates_s": round(wl.H * wl.W * wl.n * st.cycles
                                                        / (ms * 1e-3) / 1e6, 1),
                                "tol": wl.tol, "cycle_len": wl.n}
-    return res
+    checks.append(("single512_to_tol", deferred_run(u.cpu().numpy(), pr, wl, st.cycles,
+                                                    "the image")))
+    return res, checks
+
+
+def deferred_run(got, pr, wl, cycles, what):
+    """Deferred FP64 check of a GPU run of `cycles` cycles: the oracle from the same input
+    for the same number of cycles (equal cycle counts)."""
+    def check():
+        import oracle
+        ref, _, _ = oracle.inpaint(pr["u_init"], pr["mask"], pr["known"], wl.lam, wl.sigma,
+                                   wl.tau, wl.n, cycles)
+        e = fp64_error(got, ref)
+        e["sample"] = f"{what} after {cycles} cycles of {wl.n}, oracle at the same count"
+        return e
+    return check
 
 
 def batched_vs_single(eed4, torch, cycles):
@@ -354,11 +504,25 @@ def batched_vs_single(eed4, torch, cycles):
     torch.cuda.synchronize()
     ts = time.perf_counter() - t0
     diff = max(float(torch.sqrt(torch.mean((a - b) ** 2))) for a, b in zip(ub, us))
+    same = all(bool(torch.equal(a, b)) for a, b in zip(ub, us))
     upd = px * wl.n * cycles
-    return {"workload": f"batch64: 64 images, {px} px, {cycles} cycles of {wl.n}",
-            "batched_mpix_updates_s": upd / tb / 1e6, "per_image_mpix_updates_s": upd / ts / 1e6,
-            "speedup": ts / tb, "batched_ms": tb * 1e3, "per_image_ms": ts * 1e3,
-            "autotuned_shape": eed4.SHAPE_NAMES[shape], "max_rmse_between": diff}
+    res = {"workload": f"batch64: 64 images, {px} px, {cycles} cycles of {wl.n}",
+           "batched_mpix_updates_s": upd / tb / 1e6, "per_image_mpix_updates_s": upd / ts / 1e6,
+           "speedup": ts / tb, "batched_ms": tb * 1e3, "per_image_ms": ts * 1e3,
+           "autotuned_shape": eed4.SHAPE_NAMES[shape], "max_rmse_between": diff,
+           "bitwise_equal_to_per_image": same}
+    # FP64 check of two sampled images: the smallest of the batch and one in the middle
+    sizes = [q["u_init"].size for q in probs]
+    picks = [int(min(range(len(probs)), key=lambda i: sizes[i])), len(probs) // 2]
+    kept = [(i, ub[i].cpu().numpy()) for i in picks]
+
+    def check():
+        out = {}
+        for i, got in kept:
+            e = deferred_run(got, probs[i], wl, cycles, f"image {i} {probs[i]['u_init'].shape}")()
+            out[f"image_{i}"] = e
+        return out
+    return res, check
 
 
 def adjoint_probe(eed4, torch):
@@ -405,6 +569,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-workloads", action="store_true")
+    ap.add_argument("--no-out-of-cache", action="store_true")
+    ap.add_argument("--no-fp64-check", action="store_true",
+                    help="skip the FP64 oracle checks behind the fp64_error objects")
     ap.add_argument("--batched-cycles", type=int, default=40)
     ap.add_argument("--adjoint-probe", action="store_true",
                     help="backward passes only (16 x 256x256 and one 4096x4096 cycle), for "
@@ -469,38 +636,11 @@ def main():
     log(f"{st.cycles} cycles, {ms:.2f} ms (wall {wall * 1e3:.2f} ms), {value:.0f} Mpix-upd/s")
 
     # ---- kernel timing: back-to-back fused step launches on the same stream ----
-    a = u.clone()
-    b = u.clone()
-    c = u.clone()
-    e2 = torch.cuda.Event(enable_timing=True)
-    e3 = torch.cuda.Event(enable_timing=True)
     # the shape the library picked for this problem (tuned by the warmup call)
     shape = eed4.eed4_step_shape(1, H, W, pt)
     shape_name = eed4.SHAPE_NAMES[shape]
     ps = eed4.params(wl.lam, wl.sigma, wl.tau, n, 1, flags=eed4.EED4_FORCE_SHAPE(shape))
-    eed4.eed4_fsi_step(a, a, b, mask, ps, 0, stream=stream)  # warm
-    torch.cuda.synchronize()
-    def roles(k):  # same rotation as a cycle: S=a, X=b, Y=c
-        if k == 0:
-            return a, a, b
-        if k == 1:
-            return b, a, c
-        return (b, c, c) if k % 2 else (c, b, b)
-
-    # five windows of kernel_reps cycles each; the median window is reported
-    # (the first launches after a pause run at a lower clock)
-    windows = []
-    for _ in range(5):
-        launches = 0
-        e2.record(stream)
-        for _ in range(args.kernel_reps):
-            for k in range(n):
-                cur, prev, out = roles(k)
-                eed4.eed4_fsi_step(cur, prev, out, mask, ps, k, stream=stream)
-                launches += 1
-        e3.record(stream)
-        torch.cuda.synchronize()
-        windows.append(e2.elapsed_time(e3) / launches)
+    windows = step_kernel_windows(eed4, torch, u, mask, ps, n, args.kernel_reps, stream)
     kms = sorted(windows)[2]
     log("fused step windows: " + ", ".join(f"{w * 1e3:.1f}" for w in windows) + " us/launch")
     per_launch_bytes = BYTES_PER_UPDATE * H * W
@@ -512,6 +652,12 @@ def main():
     traffic = measured_traffic(kname)
     log(f"fused step kernel {kname}: {kms * 1e3:.1f} us/launch, {achieved:.0f} GB/s, "
         f"{tflops:.1f} TFLOP/s")
+    # the first cycle of the timed image from its initial state, for the FP64 check
+    u1 = u_init.clone()
+    eed4.eed4_fsi_cycle(u1, mask, known, ps, torch.zeros((1, 2), dtype=torch.float64,
+                                                         device=dev))
+    first_gpu = u1.cpu().numpy()
+    del u1
 
     out = {
         "metric": "Mpixel-updates/s of fused 4th-order EED FSI step + adjoint/forward time ratio",
@@ -536,8 +682,9 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": f"{kname} (fused FSI step)",
                      "kernel_us": round(kms * 1e3, 2),
-                     # the timed region per fused-step launch (it also holds one residual
-                     # reduction per cycle): agrees with kernel_us to a few percent
+                     # the timed region per fused-step launch; beside the step kernels it
+                     # holds one residual reduction per cycle, the initial Dirichlet fill and
+                     # the gaps between launches
                      "timed_region_us_per_launch": round(ms * 1e3 / (args.steps * n), 2),
                      "algorithmic_bytes_per_launch": per_launch_bytes,
                      "alu": {"achieved": round(tflops, 2), "peak": round(ALU_PEAK_TFLOPS, 1),
@@ -546,22 +693,99 @@ def main():
                      "kernel_source_sha": kernel_source_sha(),
                      "copy_context": copy_bandwidth(torch)},
     }
+    if not args.no_out_of_cache:
+        log("fused step on 8192x8192 (working set beyond the Infinity Cache)")
+        out["roofline"]["out_of_cache"] = out_of_cache_point(eed4, torch, wl, shape,
+                                                             max(args.kernel_reps // 4, 2),
+                                                             stream)
+    checks = []          # (path in out, deferred FP64 check)
     if not args.no_variants:
         log("tensor variants (Table 7 diffusivities x mu3 choices)")
         out["variants"] = variants_timing(eed4, torch, u, mask, wl, stream)
+        checks.append((("variants",), variant_first_cycle(eed4, torch, pr, mask, known, wl)))
     if not args.no_workloads:
         log("colour and scratch workloads (512x512)")
-        out["workloads"] = workload_throughput(eed4, torch)
+        out["workloads"], wchecks = workload_throughput(eed4, torch)
+        checks += [(("workloads", name), fn) for name, fn in wchecks]
     if not args.no_adjoint:
         log("adjoint / forward timing (16 x 256x256)")
-        out["adjoint_forward_ratio"] = adjoint_ratio(eed4, torch, args)
+        out["adjoint_forward_ratio"], fn = adjoint_ratio(eed4, torch, args)
+        checks.append((("adjoint_forward_ratio",), fn))
     if not args.no_batched:
         log("batched vs per-image (64 uneven images)")
-        out["batched"] = batched_vs_single(eed4, torch, args.batched_cycles)
+        out["batched"], fn = batched_vs_single(eed4, torch, args.batched_cycles)
+        checks.append((("batched",), fn))
+    # ---- host-only work from here on: the FP64 oracle ----
     if not args.no_cpu_baseline:
-        log("timing the FP64 oracle on the host (one cycle)")
-        out["cpu_baseline"] = cpu_baseline(pr, wl)
+        log("timing the FP64 oracle on the host (one cycle; single thread; other workloads)")
+        out["cpu_baseline"], first_ref = cpu_baseline(pr, wl)
+        e = fp64_error(first_gpu, first_ref)
+        e["sample"] = (f"first FSI cycle of the {H}x{W} workload image from its initial state, "
+                       f"kernel shape {shape_name}")
+        out["fp64_error"] = e
+    if not args.no_fp64_check:
+        log(f"FP64 oracle checks of {len(checks)} results")
+        for path, fn in checks:
+            node = out
+            for key in path:
+                node = node[key]
+            node["fp64_error"] = fn()
     print(json.dumps(out), flush=True)
+
+
+def step_kernel_windows(eed4, torch, u, mask, ps, n, reps, stream):
+    """Five windows of `reps` cycles of back-to-back eed4_fsi_step launches in the
+    buffer rotation of a cycle; returns ms per launch of each window (the first
+    launches after a pause run at a lower clock, so callers take the median)."""
+    a, b, c = u.clone(), u.clone(), u.clone()
+
+    def roles(k):  # same rotation as a cycle: S=a, X=b, Y=c
+        if k == 0:
+            return a, a, b
+        if k == 1:
+            return b, a, c
+        return (b, c, c) if k % 2 else (c, b, b)
+
+    e2 = torch.cuda.Event(enable_timing=True)
+    e3 = torch.cuda.Event(enable_timing=True)
+    eed4.eed4_fsi_step(a, a, b, mask, ps, 0, stream=stream)  # warm
+    torch.cuda.synchronize()
+    windows = []
+    for _ in range(5):
+        launches = 0
+        e2.record(stream)
+        for _ in range(reps):
+            for k in range(n):
+                cur, prev, nxt = roles(k)
+                eed4.eed4_fsi_step(cur, prev, nxt, mask, ps, k, stream=stream)
+                launches += 1
+        e3.record(stream)
+        torch.cuda.synchronize()
+        windows.append(e2.elapsed_time(e3) / launches)
+    return windows
+
+
+def out_of_cache_point(eed4, torch, wl, shape, reps, stream):
+    """The fused step of the timed kernel shape on an 8192 x 8192 image drawn on the device
+    with the same recipe: three state planes and the mask are 832 MiB, beyond the 256 MB
+    Infinity Cache, so every launch streams from HBM."""
+    from synth import make_problem_device
+    H = W = 8192
+    pr = make_problem_device(H, W, wl.n_ellipses, wl.ramp, wl.noise_std, wl.density, 8192)
+    u, mask = pr["u_init"], pr["mask"]
+    del pr["known"]
+    ps = eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, 1, flags=eed4.EED4_FORCE_SHAPE(shape))
+    windows = step_kernel_windows(eed4, torch, u, mask, ps, wl.n, reps, stream)
+    kms = sorted(windows)[2]
+    nbytes = BYTES_PER_UPDATE * H * W
+    gbs = nbytes / (kms * 1e-3) / 1e9
+    log(f"8192x8192 fused step: {kms * 1e3:.1f} us/launch, {gbs:.0f} GB/s")
+    del u, mask, pr
+    torch.cuda.empty_cache()
+    return {"H": H, "W": W, "kernel_us": round(kms * 1e3, 2), "achieved": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": nbytes,
+            "working_set_MiB": (3 * 4 + 1) * H * W // (1 << 20),
+            "windows_us": [round(w * 1e3, 1) for w in windows]}
 
 
 if __name__ == "__main__":

@@ -35,6 +35,7 @@ def _lib():
         L.oracle_radius.restype = ctypes.c_int
         L.oracle_radius.argtypes = [ctypes.c_double]
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_num_threads.argtypes = [ctypes.c_int]
         L.oracle_gauss.argtypes = [ctypes.c_double, ctypes.c_int, _dp]
         L.oracle_charbonnier.restype = ctypes.c_double
         L.oracle_charbonnier.argtypes = [ctypes.c_double, ctypes.c_double]
@@ -80,6 +81,11 @@ def _m(a):
 def num_threads() -> int:
     """OpenMP threads the oracle uses."""
     return _lib().oracle_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads for the following oracle calls (for timing on n host cores)."""
+    _lib().oracle_set_num_threads(int(n))
 
 
 def radius(sigma: float) -> int:

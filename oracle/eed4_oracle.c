@@ -61,6 +61,16 @@ int oracle_num_threads(void)
 #endif
 }
 
+/* Threads for the following calls (timing of the oracle on n host cores). */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Gaussian truncation radius used throughout: ceil(3 sigma), 0 for sigma<=0. */
 int oracle_radius(double sigma)
 {

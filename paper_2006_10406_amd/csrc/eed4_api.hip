@@ -12,6 +12,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 namespace eed4 {
@@ -162,6 +163,65 @@ int capture_graph(const std::function<int(hipStream_t)> &enqueue, hipGraphExec_t
 int capture_cycle(const CycleJob &j, hipGraphExec_t *exec)
 {
     return capture_graph([&](hipStream_t cs) { return enqueue_cycle(j, cs); }, exec);
+}
+
+// Instantiated cycle graphs of eed4_inpaint, kept across calls.  A graph
+// records only kernel launches and their arguments, so a later call whose job
+// has the same device, buffers, sizes, shape and step parameters replays it
+// without a new capture and instantiation.  The cache is bounded; beyond
+// kMaxCachedGraphs jobs a call captures its own graph and destroys it at the
+// end, as without the cache.  Entries are never evicted (a launch of an
+// evicted graph might still be in flight on another stream).
+constexpr size_t kMaxCachedGraphs = 64;
+
+struct CycleKey {
+    int dev;
+    const void *S, *X, *Y, *mask, *partials, *sums;
+    int B, H, W, R, shape, n, model;
+    float sigma, tau, lambda;      // finite (checked), so < is a strict order
+    auto tie() const
+    {
+        return std::tie(dev, S, X, Y, mask, partials, sums, B, H, W, R, shape, n, model, sigma,
+                        tau, lambda);
+    }
+    bool operator<(const CycleKey &o) const { return tie() < o.tie(); }
+};
+
+static std::mutex g_graph_mu;
+static std::map<CycleKey, hipGraphExec_t> g_graphs;
+
+// The executable graph of job j: from the cache, or captured now (and cached
+// when there is room).  *owned tells the caller to destroy it after use.
+int cycle_graph(const CycleJob &j, hipGraphExec_t *exec, bool *owned)
+{
+    CycleKey k;
+    hipError_t e = hipGetDevice(&k.dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    k.S = j.S; k.X = j.X; k.Y = j.Y; k.mask = j.mask; k.partials = j.partials; k.sums = j.sums;
+    k.B = j.B; k.H = j.H; k.W = j.W; k.R = j.R; k.shape = j.shape; k.n = j.n; k.model = j.model;
+    k.sigma = j.sigma; k.tau = j.tau; k.lambda = j.lambda;
+    {
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        auto it = g_graphs.find(k);
+        if (it != g_graphs.end()) {
+            *exec = it->second;
+            *owned = false;
+            return EED4_OK;
+        }
+    }
+    int rc = capture_cycle(j, exec);
+    if (rc != EED4_OK) return rc;
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    auto it = g_graphs.find(k);
+    if (it != g_graphs.end()) {          // another thread cached the same job meanwhile
+        *owned = true;
+    } else if (g_graphs.size() < kMaxCachedGraphs) {
+        g_graphs.emplace(k, *exec);
+        *owned = false;
+    } else {
+        *owned = true;
+    }
+    return EED4_OK;
 }
 
 struct InpaintLayout {
@@ -382,8 +442,9 @@ int eed4_inpaint(float *u, const uint8_t *mask, const float *known, int B, int H
     }
 
     hipGraphExec_t exec = nullptr;
+    bool own_exec = false;
     if (!(p->flags & EED4_NO_GRAPH)) {
-        if ((rc = capture_cycle(j, &exec)) != EED4_OK) return rc;
+        if ((rc = cycle_graph(j, &exec, &own_exec)) != EED4_OK) return rc;
     }
     std::vector<double> host(2 * (size_t)B);
     int m = 0;
@@ -423,7 +484,7 @@ int eed4_inpaint(float *u, const uint8_t *mask, const float *known, int B, int H
         const double crit = (p->flags & EED4_ABS_TOL) ? worst_abs : worst_rel;
         if (p->tol > 0.0f && crit < (double)p->tol) { ++m; break; }
     }
-    if (exec) (void)hipGraphExecDestroy(exec);
+    if (exec && own_exec) (void)hipGraphExecDestroy(exec);
     if (rc != EED4_OK) return rc;
     if (m > M) m = M;
     if (hist) {
