@@ -28,10 +28,14 @@ _u8p = ctypes.POINTER(ctypes.c_uint8)
 def _lib():
     global _LIB
     if _LIB is None:
-        src_m = os.path.getmtime(_build.SRC)
-        if not os.path.exists(_build.LIB) or os.path.getmtime(_build.LIB) < src_m:
-            _build.build()
-        L = ctypes.CDLL(_build.LIB)
+        # EED4_ORACLE_LIB names another build of the same source (the sanitizer build)
+        path = os.environ.get("EED4_ORACLE_LIB")
+        if not path:
+            src_m = os.path.getmtime(_build.SRC)
+            if not os.path.exists(_build.LIB) or os.path.getmtime(_build.LIB) < src_m:
+                _build.build()
+            path = _build.LIB
+        L = ctypes.CDLL(path)
         L.oracle_radius.restype = ctypes.c_int
         L.oracle_radius.argtypes = [ctypes.c_double]
         L.oracle_num_threads.restype = ctypes.c_int

@@ -153,20 +153,16 @@ __device__ __forceinline__ void adjoint_point(float gx, float gy, float inv_lam2
     qy = fmaf(ny, de_ds, nx * dth);
 }
 
-// acc[0] += the workgroup's sum of v (fixed order; the same workgroup index
-// owns the same slot in every launch, so the running sums are deterministic).
-__device__ __forceinline__ void block_accumulate(double v, double *scratch, double *acc)
+// The workgroup's sum of v, on thread 0: a pairwise tree over the lanes of
+// each wave, then over the four waves (FP32, fixed order: deterministic).
+__device__ __forceinline__ float block_sum(float v, float *scratch)
 {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     __syncthreads();
     if (lane == 0) scratch[wv] = v;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int i = 0; i < kThreads / 64; ++i) t += scratch[i];
-        acc[0] += t;
-    }
+    return (scratch[0] + scratch[1]) + (scratch[2] + scratch[3]);
 }
 
 template <int R>
@@ -190,7 +186,8 @@ __global__ __launch_bounds__(256) void adjoint_a_kernel(const float *u_all, cons
                                                         int H, int W, int nbx, int tiles_per_img,
                                                         StepArgs a, float il3, float lam_scale,
                                                         float *qx_all, float *qy_all,
-                                                        float *pr_all, double *lam_partials)
+                                                        float *pr_all, float *lam_partials,
+                                                        int lam_stride)
 {
     using G = AdjAGeo<R>;
     constexpr int TW = G::TW, TH = G::TH;
@@ -239,7 +236,7 @@ __global__ __launch_bounds__(256) void adjoint_a_kernel(const float *u_all, cons
 
     // ---- per point: tensor applied to Hess(r); q and de/dlambda inside the tile ----
     float txx[G::NPT], tyy[G::NPT], txy[G::NPT];
-    double dlsum = 0.0;
+    float dlsum = 0.0f;
 #pragma unroll
     for (int k = 0; k < G::NPT; ++k) {
         int p = tid + k * kThreads;
@@ -267,7 +264,7 @@ __global__ __launch_bounds__(256) void adjoint_a_kernel(const float *u_all, cons
                 size_t gi = off + (size_t)yy * W + xx;
                 qx_all[gi] = qx;
                 qy_all[gi] = qy;
-                dlsum += (double)dl;
+                dlsum += dl;
             }
         }
     }
@@ -296,8 +293,8 @@ __global__ __launch_bounds__(256) void adjoint_a_kernel(const float *u_all, cons
         }
     }
     __syncthreads();
-    block_accumulate(dlsum * (double)lam_scale, reinterpret_cast<double *>(smem),
-                     lam_partials + 2 * (size_t)tile);
+    const float tot = block_sum(dlsum, smem);
+    if (threadIdx.x == 0) lam_partials[(size_t)bimg * lam_stride + t] = lam_scale * tot;
 }
 
 template <int R>
@@ -440,7 +437,7 @@ struct AdjStripRow {
 template <int R, int ROWS, bool GEN = false>
 __device__ __forceinline__ void adjoint_strip_step(float *ring, const AdjStripArgs &s,
                                                    const float (&w)[2 * kRMax + 1],
-                                                   double *partial, float lam_scale)
+                                                   float *partial, float lam_scale)
 {
     using G = AdjStripGeo<R, ROWS>;
     constexpr int P = G::P, U = G::U, D = G::D, NU = G::NU, h = G::h;
@@ -494,7 +491,7 @@ __device__ __forceinline__ void adjoint_strip_step(float *ring, const AdjStripAr
     float txx_p = 0.0f, tyy_p = 0.0f, tyy_pp = 0.0f;         // D:A at rows g-1 (g-2 for yy)
     float z_p = 0.0f, z_pp = 0.0f;                           // (D:A)xy(l+1)-(D:A)xy(l-1)
     float qx_p = 0.0f, qy_p = 0.0f, qy_pp = 0.0f;            // q at rows g-1 (g-2 for y)
-    double dsum = 0.0;
+    float dsum = 0.0f;                                       // de/dlambda over the lane's rows
 
     RowTrack tu, tr;                  // next prefetch: u row, r row (R rows behind)
     tu.init(ybase, H);
@@ -599,7 +596,7 @@ __device__ __forceinline__ void adjoint_strip_step(float *ring, const AdjStripAr
             adjoint_point<GEN>(0.5f * gxs, 0.5f * gys, s.il2, s.il3, axx, ayy, axy, hxx, hyy, hxy,
                                tx, ty, txy, qx, qy, dl, s.model);
             const int g = ybase + i - R - 1;                          // image row of S3
-            dsum += (g >= s.Y0 && g < yend && out_lane) ? (double)dl : 0.0;
+            dsum += (g >= s.Y0 && g < yend && out_lane) ? dl : 0.0f;
             const float z = from_next_lane(txy) - from_prev_lane(txy);
 
             // ---- S4 at row g - 1: P(u) r and d = -div q ----
@@ -645,11 +642,11 @@ __device__ __forceinline__ void adjoint_strip_step(float *ring, const AdjStripAr
             }
         }
     }
+    // pairwise tree over the lanes; every lane stores lane 0's total (no
+    // lane-dependent branch)
     for (int off = 32; off > 0; off >>= 1) dsum += __shfl_down(dsum, off, 64);
-    // every lane stores lane 0's running total (no lane-dependent branch)
-    const double tot = lane0_double(dsum);
-    const double prev = partial[0];
-    partial[0] = prev + (double)lam_scale * tot;
+    const float tot = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dsum), 0));
+    partial[0] = lam_scale * tot;
 }
 
 template <int R, int ROWS, bool GEN>
@@ -658,7 +655,8 @@ __device__ __forceinline__ void adjoint_strip_body(const float *u_all, const flo
                                                    const uint8_t *__restrict__ mask_all, int H,
                                                    int W, int nstrip, int per_img, int nitems,
                                                    const StepArgs &a, float il3, float lam_scale,
-                                                   int first, int prio, double *lam_partials)
+                                                   int first, int prio, float *lam_partials,
+                                                   int lam_stride)
 {
     using G = AdjStripGeo<R, ROWS>;
     __shared__ float lds[4 * G::LDS];
@@ -687,7 +685,7 @@ __device__ __forceinline__ void adjoint_strip_body(const float *u_all, const flo
     s.model = a.model;
     s.prio = prio;
     adjoint_strip_step<R, ROWS, GEN>(lds + wave * G::LDS, s, a.w,
-                                     lam_partials + 2 * (size_t)item, lam_scale);
+                                     lam_partials + (size_t)b * lam_stride + r, lam_scale);
 }
 
 template <int R, int ROWS>
@@ -697,11 +695,12 @@ __global__ __launch_bounds__(256) void adjoint_strip_kernel(const float *u_all, 
                                                             int H, int W, int nstrip, int per_img,
                                                             int nitems, StepArgs a, float il3,
                                                             float lam_scale, int first,
-                                                            int prio, double *lam_partials)
+                                                            int prio, float *lam_partials,
+                                                            int lam_stride)
 {
     adjoint_strip_body<R, ROWS, false>(u_all, an_all, ac_all, ap_all, mask_all, H, W, nstrip,
                                        per_img, nitems, a, il3, lam_scale, first, prio,
-                                       lam_partials);
+                                       lam_partials, lam_stride);
 }
 
 // The reverse step of the tensor variants (diffusivities of Table 7, mu3
@@ -710,10 +709,12 @@ template <int R>
 __global__ __launch_bounds__(256) void adjoint_strip_model_kernel(
     const float *u_all, const float *an_all, float *ac_all, float *ap_all,
     const uint8_t *__restrict__ mask_all, int H, int W, int nstrip, int per_img, int nitems,
-    StepArgs a, float il3, float lam_scale, int first, int prio, double *lam_partials)
+    StepArgs a, float il3, float lam_scale, int first, int prio, float *lam_partials,
+    int lam_stride)
 {
     adjoint_strip_body<R, 28, true>(u_all, an_all, ac_all, ap_all, mask_all, H, W, nstrip,
-                                    per_img, nitems, a, il3, lam_scale, first, prio, lam_partials);
+                                    per_img, nitems, a, il3, lam_scale, first, prio, lam_partials,
+                                    lam_stride);
 }
 
 // ---- small helper kernels ----
@@ -724,35 +725,54 @@ __global__ __launch_bounds__(256) void fill_kernel(float *p, size_t n, float v)
         p[i] = v;
 }
 
-__global__ __launch_bounds__(256) void fill_double_kernel(double *p, size_t n)
+// One pass of the pairwise lambda reduction: out[b][c] = the sum of the c-th
+// run of 2048 values of image b's row of in (length L, zero-padded), by a
+// pairwise tree in LDS.  Passes repeat until one value per image remains.
+__global__ __launch_bounds__(1024) void pairwise_pass_kernel(const float *in, long long L,
+                                                             float *out, int nout)
 {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x)
-        p[i] = 0.0;
-}
-
-// acc[b] = fixed-order sum of image b's work-item partials (first double of each)
-__global__ __launch_bounds__(256) void lambda_reduce_kernel(const double *partials,
-                                                            int tiles_per_img, double *acc)
-{
-    __shared__ double sd[256];
-    const int b = blockIdx.x;
-    const double *p = partials + 2 * (size_t)b * tiles_per_img;
-    double d = 0.0;
-    for (int i = threadIdx.x; i < tiles_per_img; i += 256) d += p[2 * i];
-    sd[threadIdx.x] = d;
+    __shared__ float sv[2048];
+    const int c = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+    const float *p = in + (size_t)b * L + (size_t)c * 2048;
+    const long long lim = L - (long long)c * 2048;
+    sv[tid] = tid < lim ? p[tid] : 0.0f;
+    sv[tid + 1024] = tid + 1024 < lim ? p[tid + 1024] : 0.0f;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) sd[threadIdx.x] += sd[threadIdx.x + s];
+    for (int s = 1024; s > 0; s >>= 1) {
+        if (tid < s) sv[tid] = sv[tid] + sv[tid + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) acc[b] = sd[0];
+    if (tid == 0) out[(size_t)b * nout + c] = sv[0];
 }
 
-__global__ void lambda_store_kernel(const double *acc, float *out, int B)
+// Cascade of the per-cycle sums over cycles (a pairwise tree built like a
+// binary counter): slot i holds the sum of a block of 2^i cycles.  Adding the
+// j-th cycle sum merges it with the t = (trailing ones of j) lowest slots and
+// stores the block in slot t.
+__global__ void lambda_carry_kernel(const float *cyc, float *slots, int B, int t)
 {
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < B) out[b] = (float)acc[b];
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    float v = cyc[b];
+    for (int i = 0; i < t; ++i) v = slots[(size_t)i * B + b] + v;
+    slots[(size_t)t * B + b] = v;
+}
+
+// dL/dlambda = the occupied slots (the set bits of the cycle count M), largest
+// block first.
+__global__ void lambda_final_kernel(const float *slots, int B, unsigned M, float *out)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    float v = 0.0f;
+    bool any = false;
+    for (int i = 31; i >= 0; --i)
+        if ((M >> i) & 1u) {
+            const float x = slots[(size_t)i * B + b];
+            v = any ? v + x : x;
+            any = true;
+        }
+    out[b] = v;
 }
 
 // On known pixels abar0 holds the sum of ubar over every state (ubar^{0,0}
@@ -833,7 +853,8 @@ struct RevStep {
     float *ac, *ap;          // ubar^k (in place), ubar^{k-1} contribution
     float *qx, *qy, *pr;     // tile path only
     const uint8_t *mask;
-    double *lp;              // lambda partials, one slot per work item
+    float *lp;               // lambda partials of this step: image b, item r at lp[b * ls + r]
+    int ls;                  // ... image stride (cycle_len * items per image)
     int B, H, W, R, shape, first;
 };
 
@@ -844,7 +865,8 @@ static hipError_t launch_rev_tile(const RevStep &t, const StepArgs &a, float il3
     const int nbx = (t.W + kAdjTW - 1) / kAdjTW;
     const int tpi = adjoint_tiles_per_image(t.H, t.W);
     hipLaunchKernelGGL((adjoint_a_kernel<R>), dim3((unsigned)(tpi * t.B)), dim3(256), 0, s, t.u,
-                       t.an, t.mask, t.H, t.W, nbx, tpi, a, il3, ls, t.qx, t.qy, t.pr, t.lp);
+                       t.an, t.mask, t.H, t.W, nbx, tpi, a, il3, ls, t.qx, t.qy, t.pr, t.lp,
+                       t.ls);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((adjoint_b_kernel<R>), dim3((unsigned)(tpi * t.B)), dim3(256), 0, s, t.qx,
@@ -882,7 +904,7 @@ static hipError_t launch_rev_strip(const RevStep &t, const StepArgs &a, float il
     const int prio = nitems <= cap ? 1 : 0;
     hipLaunchKernelGGL((adjoint_strip_kernel<R, ROWS>), dim3(nblk), dim3(256), 0, s, t.u, t.an,
                        t.ac, t.ap, t.mask, t.H, t.W, nstrip, per_img, (int)nitems, a, il3, ls,
-                       t.first, prio, t.lp);
+                       t.first, prio, t.lp, t.ls);
     return hipGetLastError();
 }
 
@@ -900,7 +922,7 @@ static hipError_t launch_rev_model(const RevStep &t, const StepArgs &a, float il
     const int prio = nitems <= cap ? 1 : 0;
     hipLaunchKernelGGL((adjoint_strip_model_kernel<R>), dim3(nblk), dim3(256), 0, s, t.u, t.an,
                        t.ac, t.ap, t.mask, t.H, t.W, nstrip, per_img, (int)nitems, a, il3, ls,
-                       t.first, prio, t.lp);
+                       t.first, prio, t.lp, t.ls);
     return hipGetLastError();
 }
 
@@ -944,22 +966,38 @@ static hipError_t launch_fill(float *p, size_t n, float v, hipStream_t s)
     return hipGetLastError();
 }
 
-static hipError_t launch_fill_double(double *p, size_t n, hipStream_t s)
+// Pairwise sum of each image's row of L values (in[b * L + i]) into out[b],
+// through tmp1 / tmp2 (B * ceil(L / 2048) and B * ceil(L / 2048^2) floats).
+static hipError_t launch_pairwise_sum(const float *in, long long L, int B, float *tmp1,
+                                      float *tmp2, float *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(fill_double_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, n);
+    const float *src = in;
+    float *bufs[2] = {tmp1, tmp2};
+    int which = 0;
+    for (;;) {
+        const long long nout = (L + 2047) / 2048;
+        float *dst = nout == 1 ? out : bufs[which];
+        hipLaunchKernelGGL(pairwise_pass_kernel, dim3((unsigned)nout, (unsigned)B), dim3(1024), 0,
+                           s, src, L, dst, (int)nout);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess || nout == 1) return e;
+        src = dst;
+        L = nout;
+        which ^= 1;
+    }
+}
+
+static hipError_t launch_lambda_carry(const float *cyc, float *slots, int B, int t, hipStream_t s)
+{
+    hipLaunchKernelGGL(lambda_carry_kernel, dim3((B + 255) / 256), dim3(256), 0, s, cyc, slots, B,
+                       t);
     return hipGetLastError();
 }
 
-static hipError_t launch_lambda_reduce(const double *lp, int items_per_img, int B, double *acc,
-                                       hipStream_t s)
+static hipError_t launch_lambda_final(const float *slots, int B, int M, float *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(lambda_reduce_kernel, dim3(B), dim3(256), 0, s, lp, items_per_img, acc);
-    return hipGetLastError();
-}
-
-static hipError_t launch_lambda_store(const double *acc, float *out, int B, hipStream_t s)
-{
-    hipLaunchKernelGGL(lambda_store_kernel, dim3((B + 255) / 256), dim3(256), 0, s, acc, out, B);
+    hipLaunchKernelGGL(lambda_final_kernel, dim3((B + 255) / 256), dim3(256), 0, s, slots, B,
+                       (unsigned)M, out);
     return hipGetLastError();
 }
 
@@ -973,14 +1011,13 @@ static hipError_t launch_adjoint_final(const float *abar0, const uint8_t *mask, 
 
 // ---- workspace layout of eed4_backward ----
 struct BackwardLayout {
-    size_t U, an, ac, ap, qx, qy, pr, lp, acc, total;
+    size_t U, an, ac, ap, qx, qy, pr, lp, t1, t2, cyc, slots, total;
 };
 
 static BackwardLayout backward_layout(int B, int H, int W, int n, int R)
 {
     BackwardLayout L{};
     const size_t N = (size_t)B * H * W;
-    const size_t items = (size_t)max_adjoint_items(R, H, W) * B;
     size_t o = 0;
     // two sets of recompute buffers: cycle m-1 is recomputed while cycle m is reversed
     L.U = o; o = align_up(o + sizeof(float) * N * 2 * (size_t)(n > 1 ? n - 1 : 1));
@@ -990,8 +1027,15 @@ static BackwardLayout backward_layout(int B, int H, int W, int n, int R)
     L.qx = o; o = align_up(o + sizeof(float) * N);
     L.qy = o; o = align_up(o + sizeof(float) * N);
     L.pr = o; o = align_up(o + sizeof(float) * N);
-    L.lp = o; o = align_up(o + sizeof(double) * 2 * items);
-    L.acc = o; o = align_up(o + sizeof(double) * (size_t)B);
+    // lambda: one FP32 partial per work item and reverse step of a cycle, the
+    // pairwise passes over them, the cycle sum and 32 cascade slots (per image)
+    const size_t per_img = (size_t)(n > 0 ? n : 1) * (size_t)max_adjoint_items(R, H, W);
+    const size_t n1 = (per_img + 2047) / 2048, n2 = (n1 + 2047) / 2048;
+    L.lp = o; o = align_up(o + sizeof(float) * per_img * B);
+    L.t1 = o; o = align_up(o + sizeof(float) * n1 * B);
+    L.t2 = o; o = align_up(o + sizeof(float) * n2 * B);
+    L.cyc = o; o = align_up(o + sizeof(float) * (size_t)B);
+    L.slots = o; o = align_up(o + sizeof(float) * 32 * (size_t)B);
     L.total = o;
     return L;
 }
@@ -1063,7 +1107,8 @@ extern "C" int eed4_backward(const float *ckpt, const uint8_t *mask, const float
     hipStream_t s = (hipStream_t)stream;
     const size_t N = (size_t)B * H * W;
     float *Ubuf = (float *)(base + L.U);
-    double *acc = (double *)(base + L.acc);
+    float *lp = (float *)(base + L.lp), *cyc = (float *)(base + L.cyc);
+    float *slots = (float *)(base + L.slots);
     RevStep t{};
     t.an = (float *)(base + L.an);
     t.ac = (float *)(base + L.ac);
@@ -1072,7 +1117,8 @@ extern "C" int eed4_backward(const float *ckpt, const uint8_t *mask, const float
     t.qy = (float *)(base + L.qy);
     t.pr = (float *)(base + L.pr);
     t.mask = mask;
-    t.lp = (double *)(base + L.lp);
+    t.lp = lp;
+    t.ls = n * max_adjoint_items(R, H, W);     // the tuner's steps below write within this
     t.B = B;
     t.H = H;
     t.W = W;
@@ -1092,7 +1138,7 @@ extern "C" int eed4_backward(const float *ckpt, const uint8_t *mask, const float
         if ((rc = adjoint_shape(p, probe, s, &t.shape)) != EED4_OK) return rc;
     }
     const int items = adjoint_items(R, t.shape, H, W);
-    EED4_TRY(launch_fill_double(t.lp, 2 * (size_t)items * B, s), "fill");
+    t.ls = n * items;
     EED4_TRY(hipMemcpyAsync((void *)t.an, grad_u, sizeof(float) * N, hipMemcpyDeviceToDevice, s),
              "seed copy");
 
@@ -1150,6 +1196,7 @@ extern "C" int eed4_backward(const float *ckpt, const uint8_t *mask, const float
             t.ac = ac;
             t.ap = ap;
             t.first = k == 0 ? 1 : 0;
+            t.lp = lp + (size_t)k * items;
             EED4_TRY2(launch_reverse_step(t, p, k, s), "reverse step");
             // ubar^k is complete in ac; ap holds the start of ubar^{k-1}
             float *tmp = an;
@@ -1158,13 +1205,19 @@ extern "C" int eed4_backward(const float *ckpt, const uint8_t *mask, const float
             ap = tmp;
         }
         EED4_TRY2(hipEventRecord(done[m & 1], s), "event record");
+        // this cycle's lambda partials: pairwise sum per image, then into the cascade
+        const int j = M - 1 - m;                              // cycles summed before this one
+        int carries = 0;
+        while ((j >> carries) & 1) ++carries;
+        EED4_TRY2(launch_pairwise_sum(lp, (long long)n * items, B, (float *)(base + L.t1),
+                                      (float *)(base + L.t2), cyc, s), "lambda sum");
+        EED4_TRY2(launch_lambda_carry(cyc, slots, B, carries, s), "lambda cascade");
     }
 #undef EED4_TRY2
     for (auto &x : ev) (void)hipEventDestroy(x);
     if (rc2 != EED4_OK) return rc2;
     EED4_TRY(launch_adjoint_final(an, mask, grad_known, grad_init, N, s), "final");
-    EED4_TRY(launch_lambda_reduce(t.lp, items, B, acc, s), "lambda reduce");
-    EED4_TRY(launch_lambda_store(acc, grad_lambda, B, s), "lambda store");
+    EED4_TRY(launch_lambda_final(slots, B, M, grad_lambda, s), "lambda final");
 #undef EED4_TRY
     return EED4_OK;
 }

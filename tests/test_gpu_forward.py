@@ -352,3 +352,43 @@ def test_all_known_mask_is_held():
     st = eed4.eed4_inpaint(u, to_dev(mask), to_dev(pr["image"]), eed4.params(0.05, 1.0, 0.05, 10, 3))[0]
     assert np.array_equal(u.cpu().numpy(), pr["image"])
     assert st.residual == 0.0
+
+
+@pytest.mark.parametrize("shape", [2, 5])
+def test_resume_from_a_result_is_bitwise_continuation(shape):
+    # the whole FSI state between cycles is u^{m,0} (each cycle restarts with
+    # u^{m,-1} := u^{m,0}, Sec. 3.3), so a run of a cycles resumed for b more equals a run of
+    # a + b cycles bitwise, checkpoints included
+    a, b = 3, 4
+    announce(f"resume: {a} + {b} cycles vs {a + b}, shape {eed4.SHAPE_NAMES[shape]}")
+    pr = make_problem(150, 170, 10, True, 0.01, 0.05, 7070 + shape)
+    mask, known = to_dev(pr["mask"]), to_dev(pr["known"])
+    fl = eed4.EED4_FORCE_SHAPE(shape)
+    u = to_dev(pr["u_init"])
+    ck = torch.zeros((a + b, 150, 170), dtype=torch.float32, device="cuda")
+    eed4.eed4_inpaint(u, mask, known, eed4.params(0.03, 1.5, 0.05, 10, a + b, flags=fl), ckpt=ck)
+    v = to_dev(pr["u_init"])
+    ck1 = torch.zeros((a, 150, 170), dtype=torch.float32, device="cuda")
+    eed4.eed4_inpaint(v, mask, known, eed4.params(0.03, 1.5, 0.05, 10, a, flags=fl), ckpt=ck1)
+    ck2 = torch.zeros((b, 150, 170), dtype=torch.float32, device="cuda")
+    eed4.eed4_inpaint(v, mask, known, eed4.params(0.03, 1.5, 0.05, 10, b, flags=fl), ckpt=ck2)
+    torch.cuda.synchronize()
+    assert torch.equal(u, v)
+    assert torch.equal(ck[:a], ck1) and torch.equal(ck[a:], ck2)
+
+
+@pytest.mark.parametrize("tol", [0.0, 1e-4])
+def test_nan_in_known_values_is_reported(tol):
+    # a NaN among the stored grey values reaches the cycle residual: the call must return
+    # EED4_EDIVERGED (an ordinary kernel exit: the arithmetic just carries the NaN)
+    announce(f"NaN in known values, tol {tol}")
+    pr = make_problem(64, 80, 5, True, 0.01, 0.05, 99)
+    known = pr["known"].copy()
+    ky, kx = np.argwhere(pr["mask"] != 0)[len(np.argwhere(pr["mask"] != 0)) // 2]
+    known[ky, kx] = np.nan
+    u = to_dev(pr["u_init"])
+    with pytest.raises(eed4.EED4Error) as err:
+        eed4.eed4_inpaint(u, to_dev(pr["mask"]), to_dev(known),
+                          eed4.params(0.05, 1.0, 0.05, 10, 3, tol=tol))
+    assert err.value.code == eed4._lib.EED4_EDIVERGED
+    assert bool(torch.isnan(u[ky, kx]))
