@@ -5,6 +5,7 @@
 #include "eed4_internal.h"
 #include "eed4_host.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -115,16 +116,18 @@ void cycle_roles(int k, int n, float *S, float *X, float *Y, float **cur, float 
 int enqueue_cycle(const CycleJob &j, hipStream_t s)
 {
     const int n = j.n;
+    float *const dst = j.Out ? j.Out : j.S;
     for (int k = 0; k < n; ++k) {
         float *cur, *prev, *out;
         cycle_roles(k, n, j.S, j.X, j.Y, &cur, &prev, &out);
         const bool last = (k == n - 1);
+        if (last && (n > 1 || dst != j.S)) out = dst;
         StepArgs a = make_args(j.sigma, j.R, j.tau, j.lambda, k, j.model);
         hipError_t e = launch_step(j.R, j.shape, cur, prev, out, last ? j.S : nullptr, j.mask,
                                    j.B, j.H, j.W, a, last ? j.partials : nullptr, s);
         if (e != hipSuccess) return hip_fail(e, "fsi step launch");
     }
-    if (n == 1) {
+    if (n == 1 && dst == j.S) {
         hipError_t e = hipMemcpyAsync(j.S, j.X, sizeof(float) * (size_t)j.B * j.H * j.W,
                                       hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return hip_fail(e, "cycle copy");
@@ -160,9 +163,17 @@ int capture_graph(const std::function<int(hipStream_t)> &enqueue, hipGraphExec_t
     return EED4_OK;
 }
 
-int capture_cycle(const CycleJob &j, hipGraphExec_t *exec)
+int capture_cycle(const CycleJob &j, hipGraphExec_t *exec, int nc)
 {
-    return capture_graph([&](hipStream_t cs) { return enqueue_cycle(j, cs); }, exec);
+    return capture_graph(
+        [&](hipStream_t cs) {
+            for (int c = 0; c < nc; ++c) {
+                const int rc = enqueue_cycle(j, cs);
+                if (rc != EED4_OK) return rc;
+            }
+            return (int)EED4_OK;
+        },
+        exec);
 }
 
 // Instantiated cycle graphs of eed4_inpaint, kept across calls.  A graph
@@ -173,16 +184,17 @@ int capture_cycle(const CycleJob &j, hipGraphExec_t *exec)
 // end, as without the cache.  Entries are never evicted (a launch of an
 // evicted graph might still be in flight on another stream).
 constexpr size_t kMaxCachedGraphs = 64;
+constexpr int kGraphCycles = 4;    // cycles per graph when no host work sits between cycles
 
 struct CycleKey {
-    int dev;
-    const void *S, *X, *Y, *mask, *partials, *sums;
+    int dev, nc;                   // device, cycles per graph
+    const void *S, *X, *Y, *Out, *mask, *partials, *sums;
     int B, H, W, R, shape, n, model;
     float sigma, tau, lambda;      // finite (checked), so < is a strict order
     auto tie() const
     {
-        return std::tie(dev, S, X, Y, mask, partials, sums, B, H, W, R, shape, n, model, sigma,
-                        tau, lambda);
+        return std::tie(dev, nc, S, X, Y, Out, mask, partials, sums, B, H, W, R, shape, n,
+                        model, sigma, tau, lambda);
     }
     bool operator<(const CycleKey &o) const { return tie() < o.tie(); }
 };
@@ -190,14 +202,17 @@ struct CycleKey {
 static std::mutex g_graph_mu;
 static std::map<CycleKey, hipGraphExec_t> g_graphs;
 
-// The executable graph of job j: from the cache, or captured now (and cached
-// when there is room).  *owned tells the caller to destroy it after use.
-int cycle_graph(const CycleJob &j, hipGraphExec_t *exec, bool *owned)
+// The executable graph of nc cycles of job j: from the cache, or captured now
+// (and cached when there is room).  *owned tells the caller to destroy it
+// after use.
+int cycle_graph(const CycleJob &j, int nc, hipGraphExec_t *exec, bool *owned)
 {
     CycleKey k;
+    k.nc = nc;
     hipError_t e = hipGetDevice(&k.dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    k.S = j.S; k.X = j.X; k.Y = j.Y; k.mask = j.mask; k.partials = j.partials; k.sums = j.sums;
+    k.S = j.S; k.X = j.X; k.Y = j.Y; k.Out = j.Out ? j.Out : j.S; k.mask = j.mask;
+    k.partials = j.partials; k.sums = j.sums;
     k.B = j.B; k.H = j.H; k.W = j.W; k.R = j.R; k.shape = j.shape; k.n = j.n; k.model = j.model;
     k.sigma = j.sigma; k.tau = j.tau; k.lambda = j.lambda;
     {
@@ -209,7 +224,7 @@ int cycle_graph(const CycleJob &j, hipGraphExec_t *exec, bool *owned)
             return EED4_OK;
         }
     }
-    int rc = capture_cycle(j, exec);
+    int rc = capture_cycle(j, exec, nc);
     if (rc != EED4_OK) return rc;
     std::lock_guard<std::mutex> lk(g_graph_mu);
     auto it = g_graphs.find(k);
@@ -225,7 +240,7 @@ int cycle_graph(const CycleJob &j, hipGraphExec_t *exec, bool *owned)
 }
 
 struct InpaintLayout {
-    size_t X, Y, partials, sums, hist, total;
+    size_t X, Y, T, partials, sums, sums2, hist, total;
 };
 
 // residual partials: enough for the largest per-image count of any kernel shape
@@ -249,6 +264,11 @@ InpaintLayout inpaint_layout(int op, int B, int H, int W, int R, int M)
     L.Y = o; o = align_up(o + sizeof(float) * N);
     L.partials = o; o = align_up(o + sizeof(double) * 2 * tiles);
     L.sums = o; o = align_up(o + sizeof(double) * 2 * (size_t)B);
+    if (op == EED4_OP_INPAINT) {
+        // the second state buffer and residual sums of the run to a tolerance
+        L.T = o; o = align_up(o + sizeof(float) * N);
+        L.sums2 = o; o = align_up(o + sizeof(double) * 2 * (size_t)B);
+    }
     L.hist = o;
     if (op == EED4_OP_INPAINT) o = align_up(o + sizeof(double) * 2 * (size_t)B * M);
     L.total = o;
@@ -328,17 +348,17 @@ int default_step_shape(int R, int B, int H, int W)
     return waves < kMinStripWaves ? 2 : kShapeStrip;
 }
 
-// Times one inner step (k = 0, S -> X; S is not modified) of every shape and
-// remembers the fastest for this problem size.
+// Times one inner step (k = 0, S -> X; S is not modified) of every candidate
+// shape (tune_candidates) and remembers the fastest for this problem size.
 int tune_single_step(const eed4_params *p, int B, int H, int W, float *S, float *X,
                      const uint8_t *mask, hipStream_t s, int *shape)
 {
     const int R = eed4_radius(p->sigma);
     const StepArgs a = make_args(p->sigma, R, p->tau, p->lambda, 0);
     int order[kNumShapes];
-    tune_order(default_step_shape(R, B, H, W), order);
+    const int nc = tune_candidates(default_step_shape(R, B, H, W), order);
     const int rc = tune_pick(
-        order, kNumShapes, s, [](int) { return (int)EED4_OK; },
+        order, nc, s, [](int) { return (int)EED4_OK; },
         [&](int sh) { return launch_step(R, sh, S, S, X, nullptr, mask, B, H, W, a, nullptr, s); },
         "step autotune", shape, nullptr);
     if (rc != EED4_OK) return rc;
@@ -350,6 +370,178 @@ int check_ws(void *ws, size_t ws_bytes, size_t need)
 {
     if (!ws || ((uintptr_t)ws & 255) != 0 || ws_bytes < need) return EED4_EWORKSPACE;
     return EED4_OK;
+}
+
+// Pinned host memory of at least `bytes` for the residual read-backs of the
+// calling thread (asynchronous copies need page-locked memory).  Grows and is
+// kept for the thread's lifetime.
+static double *pinned_sums(size_t bytes)
+{
+    static thread_local double *buf = nullptr;
+    static thread_local size_t cap = 0;
+    if (cap < bytes) {
+        if (buf) (void)hipHostFree(buf);
+        buf = nullptr;
+        cap = 0;
+        void *q = nullptr;
+        if (hipHostMalloc(&q, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+        buf = (double *)q;
+        cap = bytes;
+    }
+    return buf;
+}
+
+// Result of a run of FSI cycles: cycles run, the last cycle's largest plain
+// and relative residual over the batch, and whether any was not finite.
+struct RunResult {
+    int cycles = 0;
+    double worst_abs = 0.0, worst_rel = 0.0;
+    bool diverged = false;
+};
+
+static void evaluate_residuals(const double *sums, int B, RunResult &r)
+{
+    r.worst_abs = r.worst_rel = 0.0;
+    for (int b = 0; b < B; ++b) {
+        const double res = std::sqrt(sums[2 * b]), nn = std::sqrt(sums[2 * b + 1]);
+        if (!std::isfinite(res) || !std::isfinite(nn)) r.diverged = true;
+        r.worst_abs = std::fmax(r.worst_abs, res);
+        r.worst_rel = std::fmax(r.worst_rel, nn > 0.0 ? res / nn : res);
+    }
+}
+
+// Cycles until the first whose residual is below tol (Sec. 3.3), or M, with
+// the stop decision one cycle behind the GPU: cycle m+1 is queued before the
+// host reads cycle m's residual, so the GPU never waits for the host.  The
+// cycles alternate between the caller's u and T (even cycles read u and end
+// in T, odd ones the reverse), so the cycle queued beyond the stop point
+// writes only the buffer that does not hold the accepted result; at the end
+// the result is copied into u when it lies in T.  That extra cycle also writes
+// its checkpoint slot (when it exists) and history slot, which the caller does
+// not read.
+static int run_to_tolerance(const CycleJob &j, float *T, double *sums2, const eed4_params *p,
+                            float *ckpt, double *hist_dev, hipStream_t s, RunResult *out)
+{
+    const int M = p->max_cycles, B = j.B;
+    const size_t N = (size_t)B * j.H * j.W;
+    CycleJob job[2] = {j, j};
+    job[0].Out = T;                                   // even cycles: u -> T
+    job[1].S = T; job[1].Out = j.S; job[1].sums = sums2;   // odd cycles: T -> u
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    bool own[2] = {false, false};
+    int rc = EED4_OK;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 2 && rc == EED4_OK && !(p->flags & EED4_NO_GRAPH); ++i)
+        rc = cycle_graph(job[i], 1, &exec[i], &own[i]);
+    double *host = rc == EED4_OK ? pinned_sums(sizeof(double) * 4 * (size_t)B) : nullptr;
+    if (rc == EED4_OK && !host) rc = hip_fail(hipErrorOutOfMemory, "pinned host buffer");
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    for (int i = 0; i < 2 && rc == EED4_OK; ++i) {
+        e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+        if (e != hipSuccess) rc = hip_fail(e, "event");
+    }
+    auto issue = [&](int m) -> int {
+        const CycleJob &c = job[m & 1];
+        if (ckpt) {
+            e = hipMemcpyAsync(ckpt + (size_t)m * N, c.S, sizeof(float) * N,
+                               hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
+        }
+        if (exec[m & 1]) {
+            e = hipGraphLaunch(exec[m & 1], s);
+            if (e != hipSuccess) return hip_fail(e, "graph launch");
+        } else {
+            const int r = enqueue_cycle(c, s);
+            if (r != EED4_OK) return r;
+        }
+        if (hist_dev) {
+            e = hipMemcpyAsync(hist_dev + 2 * (size_t)B * m, c.sums, sizeof(double) * 2 * B,
+                               hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return hip_fail(e, "history copy");
+        }
+        e = hipMemcpyAsync(host + 2 * (size_t)B * (m & 1), c.sums, sizeof(double) * 2 * B,
+                           hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipEventRecord(ev[m & 1], s);
+        return e == hipSuccess ? (int)EED4_OK : hip_fail(e, "residual read-back");
+    };
+    int m = 0;
+    if (rc == EED4_OK) rc = issue(0);
+    for (; rc == EED4_OK; ++m) {
+        if (m + 1 < M && (rc = issue(m + 1)) != EED4_OK) break;
+        e = hipEventSynchronize(ev[m & 1]);
+        if (e != hipSuccess) { rc = hip_fail(e, "residual read-back"); break; }
+        evaluate_residuals(host + 2 * (size_t)B * (m & 1), B, *out);
+        const double crit = (p->flags & EED4_ABS_TOL) ? out->worst_abs : out->worst_rel;
+        if (out->diverged || crit < (double)p->tol || m == M - 1) break;
+    }
+    out->cycles = m + 1;
+    // wait for the cycle queued beyond the stop point, then bring the result home
+    if (rc == EED4_OK && (e = hipStreamSynchronize(s)) != hipSuccess) rc = hip_fail(e, "sync");
+    if (rc == EED4_OK && (m & 1) == 0) {
+        e = hipMemcpyAsync(j.S, T, sizeof(float) * N, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) rc = hip_fail(e, "result copy");
+    }
+    if (rc != EED4_OK) (void)hipStreamSynchronize(s);   // the pinned buffer outlives queued copies
+    for (int i = 0; i < 2; ++i) {
+        if (ev[i]) (void)hipEventDestroy(ev[i]);
+        if (exec[i] && own[i]) (void)hipGraphExecDestroy(exec[i]);
+    }
+    return rc;
+}
+
+// M cycles in place on j.S with one stop-rule evaluation at the end (tol 0,
+// or a single cycle).  Without checkpoints or history nothing is read between
+// cycles: whole groups of kGraphCycles cycles run as one graph each (one
+// launch, and one gap between launches, per group), the rest one by one.  The
+// group size is fixed, so calls of any length share one cached graph.
+static int run_fixed(const CycleJob &j, int M, const eed4_params *p, float *ckpt,
+                     double *hist_dev, hipStream_t s, RunResult *out)
+{
+    const int B = j.B;
+    const size_t N = (size_t)B * j.H * j.W;
+    hipGraphExec_t exec = nullptr, multi = nullptr;
+    bool own_exec = false, own_multi = false;
+    int rc = EED4_OK;
+    hipError_t e = hipSuccess;
+    if (!(p->flags & EED4_NO_GRAPH)) rc = cycle_graph(j, 1, &exec, &own_exec);
+    int m = 0;
+    if (rc == EED4_OK && exec && !ckpt && !hist_dev && M >= kGraphCycles) {
+        rc = cycle_graph(j, kGraphCycles, &multi, &own_multi);
+        for (; rc == EED4_OK && m + kGraphCycles <= M; m += kGraphCycles) {
+            e = hipGraphLaunch(multi, s);
+            if (e != hipSuccess) rc = hip_fail(e, "graph launch");
+        }
+    }
+    for (; rc == EED4_OK && m < M; ++m) {
+        if (ckpt) {
+            e = hipMemcpyAsync(ckpt + (size_t)m * N, j.S, sizeof(float) * N,
+                               hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) { rc = hip_fail(e, "checkpoint copy"); break; }
+        }
+        if (exec) {
+            e = hipGraphLaunch(exec, s);
+            if (e != hipSuccess) { rc = hip_fail(e, "graph launch"); break; }
+        } else if ((rc = enqueue_cycle(j, s)) != EED4_OK) {
+            break;
+        }
+        if (hist_dev) {
+            e = hipMemcpyAsync(hist_dev + 2 * (size_t)B * m, j.sums, sizeof(double) * 2 * B,
+                               hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) { rc = hip_fail(e, "history copy"); break; }
+        }
+    }
+    if (rc == EED4_OK) {       // the last cycle's residual: reported, and checked for divergence
+        std::vector<double> host(2 * (size_t)B);
+        e = hipMemcpyAsync(host.data(), j.sums, sizeof(double) * 2 * B, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) rc = hip_fail(e, "residual read-back");
+        else evaluate_residuals(host.data(), B, *out);
+    }
+    out->cycles = M;
+    if (exec && own_exec) (void)hipGraphExecDestroy(exec);
+    if (multi && own_multi) (void)hipGraphExecDestroy(multi);
+    return rc;
 }
 
 // ---- static scratch of the allocation-free entry point ----
@@ -441,52 +633,15 @@ int eed4_inpaint(float *u, const uint8_t *mask, const float *known, int B, int H
         if ((rc = tune_single_step(p, B, H, W, u, j.X, mask, s, &j.shape)) != EED4_OK) return rc;
     }
 
-    hipGraphExec_t exec = nullptr;
-    bool own_exec = false;
-    if (!(p->flags & EED4_NO_GRAPH)) {
-        if ((rc = cycle_graph(j, &exec, &own_exec)) != EED4_OK) return rc;
+    RunResult res;
+    if (p->tol > 0.0f && M > 1) {
+        rc = run_to_tolerance(j, (float *)(base + L.T), (double *)(base + L.sums2), p, ckpt,
+                              hist ? hist_dev : nullptr, s, &res);
+    } else {
+        rc = run_fixed(j, M, p, ckpt, hist ? hist_dev : nullptr, s, &res);
     }
-    std::vector<double> host(2 * (size_t)B);
-    int m = 0;
-    double worst_abs = 0.0, worst_rel = 0.0;
-    bool diverged = false;
-    for (; m < M; ++m) {
-        if (ckpt) {
-            e = hipMemcpyAsync(ckpt + (size_t)m * N, u, sizeof(float) * N,
-                               hipMemcpyDeviceToDevice, s);
-            if (e != hipSuccess) { rc = hip_fail(e, "checkpoint copy"); break; }
-        }
-        if (exec) {
-            e = hipGraphLaunch(exec, s);
-            if (e != hipSuccess) { rc = hip_fail(e, "graph launch"); break; }
-        } else if ((rc = enqueue_cycle(j, s)) != EED4_OK) {
-            break;
-        }
-        if (hist) {
-            e = hipMemcpyAsync(hist_dev + 2 * (size_t)B * m, j.sums, sizeof(double) * 2 * B,
-                               hipMemcpyDeviceToDevice, s);
-            if (e != hipSuccess) { rc = hip_fail(e, "history copy"); break; }
-        }
-        const bool need_host = p->tol > 0.0f || m == M - 1;
-        if (!need_host) continue;
-        e = hipMemcpyAsync(host.data(), j.sums, sizeof(double) * 2 * B, hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) { rc = hip_fail(e, "residual read-back"); break; }
-        worst_abs = worst_rel = 0.0;
-        for (int b = 0; b < B; ++b) {
-            double r = std::sqrt(host[2 * b]), nn = std::sqrt(host[2 * b + 1]);
-            if (!std::isfinite(r) || !std::isfinite(nn)) diverged = true;
-            double rel = nn > 0.0 ? r / nn : r;
-            worst_abs = std::fmax(worst_abs, r);
-            worst_rel = std::fmax(worst_rel, rel);
-        }
-        if (diverged) { ++m; break; }
-        const double crit = (p->flags & EED4_ABS_TOL) ? worst_abs : worst_rel;
-        if (p->tol > 0.0f && crit < (double)p->tol) { ++m; break; }
-    }
-    if (exec && own_exec) (void)hipGraphExecDestroy(exec);
     if (rc != EED4_OK) return rc;
-    if (m > M) m = M;
+    const int m = res.cycles;
     if (hist) {
         std::vector<double> hd(2 * (size_t)B * m);
         e = hipMemcpyAsync(hd.data(), hist_dev, sizeof(double) * hd.size(), hipMemcpyDeviceToHost, s);
@@ -496,10 +651,10 @@ int eed4_inpaint(float *u, const uint8_t *mask, const float *known, int B, int H
     }
     if (stats) {
         stats->cycles = m;
-        stats->residual = worst_abs;
-        stats->rel_residual = worst_rel;
+        stats->residual = res.worst_abs;
+        stats->rel_residual = res.worst_rel;
     }
-    return diverged ? EED4_EDIVERGED : EED4_OK;
+    return res.diverged ? EED4_EDIVERGED : EED4_OK;
 }
 
 int eed4_fsi_cycle(float *u, const uint8_t *mask, const float *known, int B, int H, int W,

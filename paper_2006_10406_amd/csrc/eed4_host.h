@@ -12,7 +12,8 @@ namespace eed4 {
 
 // One FSI cycle over a batch of B equal-size images.
 struct CycleJob {
-    float *S, *X, *Y;          // S: caller's u; X, Y: rotation buffers
+    float *S, *X, *Y;          // S: cycle start; X, Y: rotation buffers
+    float *Out = nullptr;      // where the last step writes u^{m,n}: S (in place) when null
     const uint8_t *mask;
     int B, H, W, R, shape, n;
     float sigma, tau, lambda;
@@ -44,6 +45,26 @@ inline void tune_order(int first, int (&order)[kNumShapes])
     order[n++] = first;
     for (int sh = 0; sh < kNumShapes; ++sh)
         if (sh != first) order[n++] = sh;
+}
+
+// Candidates of the single-image tuner, `first` (the size rule's default)
+// first; returns their count.  Where the default is a strip (enough work for
+// the strips to fill the chip) the workgroup tiles are left out: they need
+// 2-3x the instructions per pixel and lose by far more than the tuner's
+// margin, and timing them would only load the GPU.  Where the default is a
+// tile the 28- and 8-row strips are the strips that can compete.
+inline int tune_candidates(int first, int (&order)[kNumShapes])
+{
+    int n = 0;
+    order[n++] = first;
+    for (int sh = 0; sh < kNumShapes; ++sh) {
+        if (sh == first) continue;
+        const bool keep = is_strip(first) ? is_strip(sh)
+                                           : (!is_strip(sh) || sh == kShapeStripShort ||
+                                              sh == kShapeStripTiny);
+        if (keep) order[n++] = sh;
+    }
+    return n;
 }
 int default_step_shape(int R, int B, int H, int W);
 
@@ -107,7 +128,7 @@ void cycle_roles(int k, int n, float *S, float *X, float *Y, float **cur, float 
                  float **out);
 int enqueue_cycle(const CycleJob &j, hipStream_t s);
 int capture_graph(const std::function<int(hipStream_t)> &enqueue, hipGraphExec_t *exec);
-int capture_cycle(const CycleJob &j, hipGraphExec_t *exec);
+int capture_cycle(const CycleJob &j, hipGraphExec_t *exec, int nc = 1);
 size_t backward_workspace(int B, int H, int W, const eed4_params *p);
 
 }  // namespace eed4

@@ -392,3 +392,32 @@ def test_nan_in_known_values_is_reported(tol):
                           eed4.params(0.05, 1.0, 0.05, 10, 3, tol=tol))
     assert err.value.code == eed4._lib.EED4_EDIVERGED
     assert bool(torch.isnan(u[ky, kx]))
+
+
+def test_run_to_tolerance_equals_fixed_cycle_run():
+    # a run to a tolerance queues each next cycle before reading the residual and alternates
+    # two state buffers; its state, checkpoints and residual history must equal a run of the
+    # same number of fixed cycles bitwise, whichever buffer the last cycle ended in
+    pr = make_problem(120, 150, 8, True, 0.01, 0.05, 5150)
+    mask, known = to_dev(pr["mask"]), to_dev(pr["known"])
+    lam, sigma, tau, n, M = 0.04, 1.5, 0.05, 10, 60
+    seen = set()
+    for tol in (3e-3, 2e-3, 1.5e-3, 1e-3):
+        announce(f"run to tolerance {tol} vs fixed cycles, 120x150")
+        u = to_dev(pr["u_init"])
+        ck = torch.full((M, 120, 150), -7.0, dtype=torch.float32, device="cuda")
+        st, hist = eed4.eed4_inpaint(u, mask, known, eed4.params(lam, sigma, tau, n, M, tol=tol),
+                                     ckpt=ck, history=True)
+        c = st.cycles
+        assert 1 < c < M
+        v = to_dev(pr["u_init"])
+        ck2 = torch.zeros((c, 120, 150), dtype=torch.float32, device="cuda")
+        st2, hist2 = eed4.eed4_inpaint(v, mask, known, eed4.params(lam, sigma, tau, n, c),
+                                       ckpt=ck2, history=True)
+        torch.cuda.synchronize()
+        assert torch.equal(u, v)
+        assert torch.equal(ck[:c], ck2)
+        assert np.array_equal(hist, hist2)
+        assert st.residual == st2.residual and st.rel_residual == st2.rel_residual
+        seen.add(c % 2)
+    assert seen == {0, 1}, "both buffer parities should be covered"
