@@ -20,8 +20,10 @@
 //  - workgroup tiles: pass A computes P(u) r, q and de/dlambda into global
 //    buffers; pass B applies C^T q = K_sigma (-div q) and the update;
 //  - wave strips (one launch): a wave streams down a strip and carries every
-//    intermediate in registers and a per-wave LDS ring, as the forward strip
-//    kernel does.
+//    intermediate in registers and per-wave LDS, as the forward strip kernel
+//    does.  It reads the presmoothed image K_sigma * u^k, which the forward
+//    recompute keeps, instead of blurring u^k again: that saves the blur's
+//    arithmetic and R rows of halo at each end of a segment.
 // Known pixels: r is 0 there, so ubar on a known pixel feeds nothing but fbar.
 // Both implementations therefore keep on known pixels the running sum of ubar
 // over the reverse steps done so far; fbar is that sum at the end.  lambdabar
@@ -386,38 +388,34 @@ __global__ __launch_bounds__(256) void adjoint_b_kernel(const float *qx_all, con
 // ---- fused reverse step on wave strips ----
 //
 // A wave owns 64 consecutive columns c = X0-2-R .. X0+61-R (one per lane) and
-// streams down the rows of a segment.  For each stream row i it
-//   S1  stages u^k(i) in a per-wave LDS ring and takes the x pass of the
-//       presmoothing;
-//   S2  completes the y pass at row i-R;
-//   S3  at row g = i-R-1: gradient of u_sigma, Hessian of u (ring), Hessian of
-//       r = mbar ubar^{k+1} (r rows in registers, lane neighbours by DPP), and
-//       the adjoint point quantities D:A, q, de/dlambda;
+// streams down the rows of a segment.  For each stream row i it loads the
+// presmoothed image v = K_sigma * u^k (kept by the forward recompute), u^k and
+// r = mbar ubar^{k+1} of the row, then
+//   S3  at row g = i-1: gradient of v, Hessians of u and of r (the last three
+//       rows in registers, lane neighbours by DPP) and the adjoint point
+//       quantities D:A, q, de/dlambda;
 //   S4  at row g-1: P(u) r from the outer differences of D:A, and
 //       d = -div q, whose x pass goes through a one-row LDS buffer into a
 //       register window;
-//   S5  at row o = i-2R-2: y pass of d (C^T q) and the reverse update.
+//   S5  at row o = i-R-2: y pass of d (C^T q) and the reverse update.
 // Lanes R+2 .. 61-R own output columns (60-2R per wave).  The input halo is
-// 2R+2 rows each way.
+// R+2 rows each way: R+1 for the y pass of d and one more for q.
 template <int R, int ROWS>
 struct AdjStripGeo {
-    static constexpr int P = 2 * R + 1;                       // window length
-    static constexpr int U = P * ((R + 3 + P - 1) / P);       // unroll = LDS ring depth
-    static constexpr int D = U;
-    static constexpr int h = 2 * R + 2;                       // input row halo
+    static constexpr int P = 2 * R + 1;                       // d window length
+    static constexpr int U = P;                               // unroll (window slots constant)
+    static constexpr int h = R + 2;                           // input row halo
     static constexpr int hc = R + 2;                          // first output lane
     static constexpr int SW = 64 - 2 * hc;                    // output columns per wave
-    static constexpr int NU = 64 + 2 * R;                     // staged u columns per row
-    static constexpr int CS = D | 1;                          // ring column stride (odd)
     static constexpr int ND = 64 + 2 * R;                     // d row, R pad on each side
-    static constexpr int M = (ROWS + 2 * h - 2 * R + U - 1) / U;
-    static constexpr int NROW = 2 * R + M * U;                // rows streamed per wave
+    static constexpr int M = (ROWS + 2 * h + U - 1) / U;      // main-loop iterations
+    static constexpr int NROW = M * U;                        // rows streamed per wave
     static constexpr int OH = NROW - 2 * h;                   // output rows per wave
-    static constexpr int LDS = (NU + 2) * CS + ND + P * 64;   // floats of LDS per wave
+    static constexpr int LDS = ND + P * 64;                   // floats of LDS per wave
 };
 
 struct AdjStripArgs {
-    const float *u, *an;        // u^k, ubar^{k+1}
+    const float *v, *u, *an;    // K_sigma * u^k, u^k, ubar^{k+1}
     float *ac, *ap;             // ubar^k (accumulated in place), ubar^{k-1} contribution
     const uint8_t *mask;
     int H, W, X0, Y0;
@@ -427,20 +425,20 @@ struct AdjStripArgs {
     int prio;                   // lower the issue priority along the segment
 };
 
-// Global loads of one stream row: u^k of the row, r of the row R above it,
-// and ubar^{k+1}, ubar^k and the mask of the output row it serves.
+// Global loads of one stream row: v, u^k and r of the row itself, and
+// ubar^{k+1}, ubar^k and the mask of the output row it serves.
 struct AdjStripRow {
-    float a, b, rn, oa, oc;
+    float v, u, rn, oa, oc;
     unsigned rmk, omk;
 };
 
 template <int R, int ROWS, bool GEN = false>
-__device__ __forceinline__ void adjoint_strip_step(float *ring, const AdjStripArgs &s,
+__device__ __forceinline__ void adjoint_strip_step(float *lds, const AdjStripArgs &s,
                                                    const float (&w)[2 * kRMax + 1],
                                                    float *partial, float lam_scale)
 {
     using G = AdjStripGeo<R, ROWS>;
-    constexpr int P = G::P, U = G::U, D = G::D, NU = G::NU, h = G::h;
+    constexpr int P = G::P, U = G::U, h = G::h;
     const int lane = threadIdx.x & 63;
     const int H = s.H, W = s.W;
     const unsigned W4 = 4u * (unsigned)W;
@@ -451,6 +449,7 @@ __device__ __forceinline__ void adjoint_strip_step(float *ring, const AdjStripAr
     const int b0 = ybase > 0 ? ybase : 0;
     const int nb = (H - b0 < G::NROW) ? H - b0 : G::NROW;
     const size_t base = (size_t)b0 * W;
+    const __amdgpu_buffer_rsrc_t rs_v = buffer_rsrc(s.v + base, (unsigned)nb * W4);
     const __amdgpu_buffer_rsrc_t rs_u = buffer_rsrc(s.u + base, (unsigned)nb * W4);
     const __amdgpu_buffer_rsrc_t rs_an = buffer_rsrc(s.an + base, (unsigned)nb * W4);
     const __amdgpu_buffer_rsrc_t rs_ac = buffer_rsrc(s.ac + base, (unsigned)nb * W4);
@@ -460,48 +459,37 @@ __device__ __forceinline__ void adjoint_strip_step(float *ring, const AdjStripAr
     const float keep_back = s.first ? 1.0f : 0.0f;
     const __amdgpu_buffer_rsrc_t rs_m = buffer_rsrc(s.mask + base, (unsigned)nb * (unsigned)W);
 
-    const int c0 = s.X0 - G::hc;                              // column of lane 0
-    const unsigned ca = 4u * (unsigned)mirror_reflect(c0 - R + lane, W);
-    const int lb = R > 0 ? lane % (2 * R > 0 ? 2 * R : 1) : 0;
-    const unsigned cb = 4u * (unsigned)mirror_reflect(c0 - R + 64 + lb, W);
-    const int cl = c0 + lane;                                 // this lane's column
+    const int cl = s.X0 - G::hc + lane;                       // this lane's column
     const unsigned cm = (unsigned)mirror_reflect(cl, W);      // ... mirrored into the image
     const bool out_lane = lane >= G::hc && lane < 64 - G::hc && cl < W;
     const unsigned vo4 = out_lane ? 4u * (unsigned)cl : kOffNone;
     const unsigned vo1 = out_lane ? (unsigned)cl : kOffNone;
     const int yend = s.Y0 + G::OH < H ? s.Y0 + G::OH : H;     // rows owned: [Y0, yend)
 
-    // u ring column-major as in the forward strip: staged column c of ring
-    // row r at (c + 1) * CS + r; then the d row (lane l at l + R); then P(u) r
-    // of the last P rows (slot j, lane l at j * 64 + l), kept in LDS rather
-    // than registers: a slot is read R rows after it is written, and the
-    // register copy would cost far more VGPRs than its P values (178 -> 121 at
-    // R = 6, i.e. 2 -> 4 waves per SIMD)
-    constexpr int CS = G::CS;
-    float *col = ring + (lane + 1) * CS;
-    float *bcol = ring + (64 + lb + 1) * CS;
-    float *dw = ring + (NU + 2) * CS + lane;
-    float *prr = ring + (NU + 2) * CS + G::ND + lane;         // P(u) r, row j in slot j % P
+    // the d row (lane l at l + R), then P(u) r of the last P rows (slot j,
+    // lane l at j * 64 + l): a slot is read R rows after it is written, and a
+    // register window would cost more VGPRs than its P values
+    float *dw = lds + lane;
+    float *prr = lds + G::ND + lane;
 
-    float win[P], dwin[P];            // x-pass u, x-pass d; row j in slot j % P
+    float dwin[P];                    // x-pass d; stream row j in slot j % P
 #pragma unroll
-    for (int j = 0; j < P; ++j) win[j] = dwin[j] = 0.0f;
-    float v_m1 = 0.0f, v_m2 = 0.0f;                          // v at rows g, g-1 (before update)
-    float r_m1 = 0.0f, r_0 = 0.0f;                           // r at rows g-1, g
+    for (int j = 0; j < P; ++j) dwin[j] = 0.0f;
+    float v_m1 = 0.0f, v_m2 = 0.0f;                          // v at rows g, g-1
+    float u_m1 = 0.0f, u_m2 = 0.0f;                          // u at rows g, g-1
+    float r_m1 = 0.0f, r_m2 = 0.0f;                          // r at rows g, g-1
     float txx_p = 0.0f, tyy_p = 0.0f, tyy_pp = 0.0f;         // D:A at rows g-1 (g-2 for yy)
     float z_p = 0.0f, z_pp = 0.0f;                           // (D:A)xy(l+1)-(D:A)xy(l-1)
     float qx_p = 0.0f, qy_p = 0.0f, qy_pp = 0.0f;            // q at rows g-1 (g-2 for y)
     float dsum = 0.0f;                                       // de/dlambda over the lane's rows
 
-    RowTrack tu, tr;                  // next prefetch: u row, r row (R rows behind)
-    tu.init(ybase, H);
-    tr.init(ybase - R, H);
+    RowTrack ty;                      // next prefetch: its mirrored image row
+    ty.init(ybase, H);
     int on = ybase - h;                                       // output row it serves
     auto prefetch = [&](AdjStripRow &r) {
-        const unsigned su = (unsigned)((tu.y > b0 ? tu.y : b0) - b0) * W4;
-        r.a = buf_f32(rs_u, ca, su);
-        if constexpr (R > 0) r.b = buf_f32(rs_u, cb, su);
-        const unsigned sr = (unsigned)((tr.y > b0 ? tr.y : b0) - b0);
+        const unsigned sr = (unsigned)((ty.y > b0 ? ty.y : b0) - b0);
+        r.v = buf_f32(rs_v, 4u * cm, sr * W4);
+        r.u = buf_f32(rs_u, 4u * cm, sr * W4);
         r.rn = buf_f32(rs_an, 4u * cm, sr * W4);
         r.rmk = __builtin_amdgcn_raw_buffer_load_b8(rs_m, cm, sr * (unsigned)W, 0);
         int oc = on < b0 ? b0 : on;                           // clamped; unused rows are not stored
@@ -510,31 +498,12 @@ __device__ __forceinline__ void adjoint_strip_step(float *ring, const AdjStripAr
         r.oa = buf_f32(rs_an, vo4, ro * W4);
         r.oc = buf_f32(rs_ac, vo4, ro * W4);
         r.omk = __builtin_amdgcn_raw_buffer_load_b8(rs_m, vo1, ro * (unsigned)W, 0);
-        tu.next(H);
-        tr.next(H);
+        ty.next(H);
         ++on;
     };
     AdjStripRow r0, r1;
-    r0.b = r1.b = 0.0f;
     prefetch(r0);
     prefetch(r1);
-
-    // ---- prologue: stream rows 0 .. 2R-1 (x pass; r rows roll through) ----
-#pragma unroll
-    for (int i = 0; i < 2 * R; ++i) {
-        const AdjStripRow cur = r0;
-        r0 = r1;
-        prefetch(r1);
-        col[i % D] = cur.a;
-        bcol[i % D] = cur.b;
-        wave_lds_sync();
-        float acc = w[0] * col[i % D];
-#pragma unroll
-        for (int j = 1; j <= 2 * R; ++j) acc = fmaf(w[j], col[j * CS + i % D], acc);
-        win[i % P] = acc;
-        r_m1 = r_0;
-        r_0 = cur.rmk ? 0.0f : cur.rn;
-    }
 
 #pragma unroll 1
     for (int it = 0; it < G::M; ++it) {
@@ -542,8 +511,7 @@ __device__ __forceinline__ void adjoint_strip_step(float *ring, const AdjStripAr
         // their segment yield issue slots to those behind, as in the forward
         // strip; when the launch needs more than one round of waves the host
         // leaves this off (late waves would then hold the top priority).  Only
-        // the short segments, which small problems use, carry the code: in the
-        // 64- and 136-row kernels even the untaken branch cost 4 % at 4096^2.
+        // the short segments, which small problems use, carry the code.
         if (ROWS <= 28 && s.prio) {
             const int left = G::M - it;
             if (left >= 4) __builtin_amdgcn_s_setprio(3);
@@ -553,67 +521,51 @@ __device__ __forceinline__ void adjoint_strip_step(float *ring, const AdjStripAr
         }
 #pragma unroll
         for (int ph = 0; ph < U; ++ph) {
-            const int i = 2 * R + it * U + ph;               // stream row (wave-uniform)
+            const int i = it * U + ph;                        // stream row (wave-uniform)
             const AdjStripRow cur = r0;
             r0 = r1;
             prefetch(r1);
 
-            // ---- S1: stage u^k row i, x pass ----
-            const int sr = (2 * R + ph) % D;                 // constants once unrolled
-            col[sr] = cur.a;
-            if constexpr (R > 0) bcol[sr] = cur.b;
-            wave_lds_sync();
-            float acc = w[0] * col[sr];
-#pragma unroll
-            for (int j = 1; j <= 2 * R; ++j) acc = fmaf(w[j], col[j * CS + sr], acc);
-            win[(2 * R + ph) % P] = acc;
-
-            // ---- S2: y pass at stream row i - R ----
-            float v = w[0] * win[ph % P];
-#pragma unroll
-            for (int j = 1; j <= 2 * R; ++j) v = fmaf(w[j], win[(ph + j) % P], v);
-
-            // ---- S3 at row g = i - R - 1 ----
+            // ---- S3 at row g = i - 1 (rows g-1, g, g+1: m2, m1, this row) ----
+            const float v_p1 = cur.v, u_p1 = cur.u;
+            const float r_p1 = cur.rmk ? 0.0f : cur.rn;
             const float gxs = from_next_lane(v_m1) - from_prev_lane(v_m1);  // 2 gx
-            const float gys = v - v_m2;                                      // 2 gy
-            v_m2 = v_m1;
-            v_m1 = v;
-            const float *um = col + R * CS + (R - 2 + ph + D) % D;     // rows g-1, g, g+1
-            const float *u0 = col + R * CS + (R - 1 + ph + D) % D;
-            const float *up = col + R * CS + (R + ph) % D;
-            const float uc = u0[0];
-            const float hxx = fmaf(-2.0f, uc, u0[-CS] + u0[CS]);
-            const float hyy = fmaf(-2.0f, uc, um[0] + up[0]);
-            const float hxy = 0.25f * ((up[CS] + um[-CS]) - (up[-CS] + um[CS]));
-            const float r_p1 = cur.rmk ? 0.0f : cur.rn;                // r at row g + 1
-            const float axx = fmaf(-2.0f, r_0, from_prev_lane(r_0) + from_next_lane(r_0));
-            const float ayy = fmaf(-2.0f, r_0, r_m1 + r_p1);
+            const float gys = v_p1 - v_m2;                                   // 2 gy
+            const float hxx = fmaf(-2.0f, u_m1, from_prev_lane(u_m1) + from_next_lane(u_m1));
+            const float hyy = fmaf(-2.0f, u_m1, u_m2 + u_p1);
+            const float hxy = 0.25f * ((from_next_lane(u_p1) + from_prev_lane(u_m2)) -
+                                       (from_prev_lane(u_p1) + from_next_lane(u_m2)));
+            const float axx = fmaf(-2.0f, r_m1, from_prev_lane(r_m1) + from_next_lane(r_m1));
+            const float ayy = fmaf(-2.0f, r_m1, r_m2 + r_p1);
             const float axy = 0.25f * ((from_next_lane(r_p1) - from_prev_lane(r_p1)) -
-                                       (from_next_lane(r_m1) - from_prev_lane(r_m1)));
-            r_m1 = r_0;
-            r_0 = r_p1;
-            float tx, ty, txy, qx, qy, dl;
+                                       (from_next_lane(r_m2) - from_prev_lane(r_m2)));
+            v_m2 = v_m1;
+            v_m1 = v_p1;
+            u_m2 = u_m1;
+            u_m1 = u_p1;
+            r_m2 = r_m1;
+            r_m1 = r_p1;
+            float tx, ty_, txy, qx, qy, dl;
             adjoint_point<GEN>(0.5f * gxs, 0.5f * gys, s.il2, s.il3, axx, ayy, axy, hxx, hyy, hxy,
-                               tx, ty, txy, qx, qy, dl, s.model);
-            const int g = ybase + i - R - 1;                          // image row of S3
+                               tx, ty_, txy, qx, qy, dl, s.model);
+            const int g = ybase + i - 1;                              // image row of S3
             dsum += (g >= s.Y0 && g < yend && out_lane) ? dl : 0.0f;
             const float z = from_next_lane(txy) - from_prev_lane(txy);
 
             // ---- S4 at row g - 1: P(u) r and d = -div q ----
             const float sxx = from_prev_lane(txx_p) + from_next_lane(txx_p);
-            const float pr = fmaf(-2.0f, txx_p + tyy_p, sxx + (tyy_pp + ty)) + 0.5f * (z - z_pp);
+            const float pr = fmaf(-2.0f, txx_p + tyy_p, sxx + (tyy_pp + ty_)) + 0.5f * (z - z_pp);
             const float d = -0.5f * ((from_next_lane(qx_p) - from_prev_lane(qx_p)) + (qy - qy_pp));
             dw[R] = d;
             wave_lds_sync();
             float dx = w[0] * dw[0];
 #pragma unroll
             for (int j = 1; j <= 2 * R; ++j) dx = fmaf(w[j], dw[j], dx);
-            constexpr int kP = P;                                     // slot of row i - R - 2
-            const int jd = ((R - 2 + ph) % kP + kP) % kP;
+            const int jd = ((ph - 2) % P + P) % P;                    // slot of stream row i - 2
             dwin[jd] = dx;
             prr[jd * 64] = pr;
             tyy_pp = tyy_p;
-            tyy_p = ty;
+            tyy_p = ty_;
             txx_p = tx;
             z_pp = z_p;
             z_p = z;
@@ -621,14 +573,14 @@ __device__ __forceinline__ void adjoint_strip_step(float *ring, const AdjStripAr
             qy_p = qy;
             qx_p = qx;
 
-            // ---- S5: output row o (stream row i - 2R - 2) ----
+            // ---- S5: output row o (stream row i - h) ----
             const int o = ybase + i - h;
             if (i >= 2 * h && o < H) {
-                float cq = 0.0f;                                     // rows o-R .. o+R
+                float cq = 0.0f;                                     // stream rows i-h-R .. i-2
 #pragma unroll
                 for (int j = 0; j <= 2 * R; ++j)
-                    cq = fmaf(w[j], dwin[((ph - R - 2 + j) % kP + kP) % kP], cq);
-                const float pro = prr[((ph - 2) % kP + kP) % kP * 64];
+                    cq = fmaf(w[j], dwin[((ph - h - R + j) % P + P) % P], cq);
+                const float pro = prr[((ph - h) % P + P) % P * 64];
                 const float anv = cur.oa;
                 const bool mk = cur.omk != 0;
                 const float rv = mk ? 0.0f : anv;
@@ -650,7 +602,8 @@ __device__ __forceinline__ void adjoint_strip_step(float *ring, const AdjStripAr
 }
 
 template <int R, int ROWS, bool GEN>
-__device__ __forceinline__ void adjoint_strip_body(const float *u_all, const float *an_all,
+__device__ __forceinline__ void adjoint_strip_body(const float *v_all, const float *u_all,
+                                                   const float *an_all,
                                                    float *ac_all, float *ap_all,
                                                    const uint8_t *__restrict__ mask_all, int H,
                                                    int W, int nstrip, int per_img, int nitems,
@@ -668,6 +621,7 @@ __device__ __forceinline__ void adjoint_strip_body(const float *u_all, const flo
     const int seg = r / nstrip, strip = r - seg * nstrip;
     const size_t off = (size_t)b * H * W;
     AdjStripArgs s;
+    s.v = v_all + off;
     s.u = u_all + off;
     s.an = an_all + off;
     s.ac = ac_all + off;
@@ -689,7 +643,8 @@ __device__ __forceinline__ void adjoint_strip_body(const float *u_all, const flo
 }
 
 template <int R, int ROWS>
-__global__ __launch_bounds__(256) void adjoint_strip_kernel(const float *u_all, const float *an_all,
+__global__ __launch_bounds__(256) void adjoint_strip_kernel(const float *v_all, const float *u_all,
+                                                            const float *an_all,
                                                             float *ac_all, float *ap_all,
                                                             const uint8_t *__restrict__ mask_all,
                                                             int H, int W, int nstrip, int per_img,
@@ -698,7 +653,7 @@ __global__ __launch_bounds__(256) void adjoint_strip_kernel(const float *u_all, 
                                                             int prio, float *lam_partials,
                                                             int lam_stride)
 {
-    adjoint_strip_body<R, ROWS, false>(u_all, an_all, ac_all, ap_all, mask_all, H, W, nstrip,
+    adjoint_strip_body<R, ROWS, false>(v_all, u_all, an_all, ac_all, ap_all, mask_all, H, W, nstrip,
                                        per_img, nitems, a, il3, lam_scale, first, prio,
                                        lam_partials, lam_stride);
 }
@@ -707,12 +662,12 @@ __global__ __launch_bounds__(256) void adjoint_strip_kernel(const float *u_all, 
 // choices of Sec. 3.1) on strips of >= 28 rows.
 template <int R>
 __global__ __launch_bounds__(256) void adjoint_strip_model_kernel(
-    const float *u_all, const float *an_all, float *ac_all, float *ap_all,
+    const float *v_all, const float *u_all, const float *an_all, float *ac_all, float *ap_all,
     const uint8_t *__restrict__ mask_all, int H, int W, int nstrip, int per_img, int nitems,
     StepArgs a, float il3, float lam_scale, int first, int prio, float *lam_partials,
     int lam_stride)
 {
-    adjoint_strip_body<R, 28, true>(u_all, an_all, ac_all, ap_all, mask_all, H, W, nstrip,
+    adjoint_strip_body<R, 28, true>(v_all, u_all, an_all, ac_all, ap_all, mask_all, H, W, nstrip,
                                     per_img, nitems, a, il3, lam_scale, first, prio, lam_partials,
                                     lam_stride);
 }
@@ -849,6 +804,7 @@ static int max_adjoint_items(int R, int H, int W)
 
 // Buffers of one reverse step.
 struct RevStep {
+    const float *v;          // K_sigma * u^k (strip path only)
     const float *u, *an;     // u^k, ubar^{k+1}
     float *ac, *ap;          // ubar^k (in place), ubar^{k-1} contribution
     float *qx, *qy, *pr;     // tile path only
@@ -902,7 +858,7 @@ static hipError_t launch_rev_strip(const RevStep &t, const StepArgs &a, float il
     // the issue-priority schedule only when every wave is resident at once
     static const long long cap = resident_waves(adjoint_strip_kernel<R, ROWS>);
     const int prio = nitems <= cap ? 1 : 0;
-    hipLaunchKernelGGL((adjoint_strip_kernel<R, ROWS>), dim3(nblk), dim3(256), 0, s, t.u, t.an,
+    hipLaunchKernelGGL((adjoint_strip_kernel<R, ROWS>), dim3(nblk), dim3(256), 0, s, t.v, t.u, t.an,
                        t.ac, t.ap, t.mask, t.H, t.W, nstrip, per_img, (int)nitems, a, il3, ls,
                        t.first, prio, t.lp, t.ls);
     return hipGetLastError();
@@ -920,7 +876,7 @@ static hipError_t launch_rev_model(const RevStep &t, const StepArgs &a, float il
     const unsigned nblk = (unsigned)((nitems + 3) / 4);
     static const long long cap = resident_waves(adjoint_strip_model_kernel<R>);
     const int prio = nitems <= cap ? 1 : 0;
-    hipLaunchKernelGGL((adjoint_strip_model_kernel<R>), dim3(nblk), dim3(256), 0, s, t.u, t.an,
+    hipLaunchKernelGGL((adjoint_strip_model_kernel<R>), dim3(nblk), dim3(256), 0, s, t.v, t.u, t.an,
                        t.ac, t.ap, t.mask, t.H, t.W, nstrip, per_img, (int)nitems, a, il3, ls,
                        t.first, prio, t.lp, t.ls);
     return hipGetLastError();
@@ -1011,7 +967,7 @@ static hipError_t launch_adjoint_final(const float *abar0, const uint8_t *mask, 
 
 // ---- workspace layout of eed4_backward ----
 struct BackwardLayout {
-    size_t U, an, ac, ap, qx, qy, pr, lp, t1, t2, cyc, slots, total;
+    size_t U, V, an, ac, ap, qx, qy, pr, lp, t1, t2, cyc, slots, total;
 };
 
 static BackwardLayout backward_layout(int B, int H, int W, int n, int R)
@@ -1021,6 +977,8 @@ static BackwardLayout backward_layout(int B, int H, int W, int n, int R)
     size_t o = 0;
     // two sets of recompute buffers: cycle m-1 is recomputed while cycle m is reversed
     L.U = o; o = align_up(o + sizeof(float) * N * 2 * (size_t)(n > 1 ? n - 1 : 1));
+    // ... and K_sigma * u^{m,k}, k = 0 .. n-1, for the strip reverse step
+    L.V = o; o = align_up(o + sizeof(float) * N * 2 * (size_t)(n > 0 ? n : 1));
     L.an = o; o = align_up(o + sizeof(float) * N);
     L.ac = o; o = align_up(o + sizeof(float) * N);
     L.ap = o; o = align_up(o + sizeof(float) * N);
@@ -1131,12 +1089,17 @@ extern "C" int eed4_backward(const float *ckpt, const uint8_t *mask, const float
         if (e != hipSuccess) return hip_fail(e, what);       \
     } while (0)
 
+    float *Vbuf = (float *)(base + L.V);
     {   // choose the reverse-step kernel (the timing runs write only scratch)
         RevStep probe = t;
         probe.u = ckpt + (size_t)(M - 1) * N;
         probe.an = grad_u;
+        probe.v = Vbuf;
+        const StepArgs a0 = make_args(p->sigma, R, p->tau, p->lambda, 0, model_of_flags(p->flags));
+        EED4_TRY(launch_blur(R, probe.u, Vbuf, B, H, W, a0, s), "presmoothing");
         if ((rc = adjoint_shape(p, probe, s, &t.shape)) != EED4_OK) return rc;
     }
+    const bool keep_v = is_strip(t.shape);      // the strip reverse step reads K_sigma * u^k
     const int items = adjoint_items(R, t.shape, H, W);
     t.ls = n * items;
     EED4_TRY(hipMemcpyAsync((void *)t.an, grad_u, sizeof(float) * N, hipMemcpyDeviceToDevice, s),
@@ -1160,17 +1123,30 @@ extern "C" int eed4_backward(const float *ckpt, const uint8_t *mask, const float
     hipEvent_t *rec = ev, *done = ev + 2, start = ev[4];
     const size_t nU = (size_t)(n > 1 ? n - 1 : 1);
     float *Uset[2] = {Ubuf, Ubuf + nU * N};
+    float *Vset[2] = {Vbuf, Vbuf + (size_t)n * N};
     std::vector<const float *> Ur[2] = {std::vector<const float *>(n), std::vector<const float *>(n)};
-    auto recompute = [&](int m) -> hipError_t {   // u^{m,1..n-1} from the checkpoint, on s1
+    // u^{m,1..n-1} from the checkpoint, on s1, and (strip reverse step) v^{m,k} =
+    // K_sigma * u^{m,k} for k = 0 .. n-1: the steps keep the v they compute, and
+    // the last one, which no recomputed step forms, comes from the blur kernel
+    auto recompute = [&](int m) -> hipError_t {
         std::vector<const float *> &U = Ur[m & 1];
+        float *V = Vset[m & 1];
         U[0] = ckpt + (size_t)m * N;
         for (int k = 0; k + 1 < n; ++k) {
             float *out = Uset[m & 1] + (size_t)k * N;
             StepArgs a = make_args(p->sigma, R, p->tau, p->lambda, k, model_of_flags(p->flags));
-            hipError_t r = launch_step(R, fshape, U[k], U[k > 0 ? k - 1 : 0], out, nullptr, mask,
-                                       B, H, W, a, nullptr, s1);
+            hipError_t r = keep_v
+                ? launch_step_keepv(R, fshape, U[k], U[k > 0 ? k - 1 : 0], out, V + (size_t)k * N,
+                                    mask, B, H, W, a, s1)
+                : launch_step(R, fshape, U[k], U[k > 0 ? k - 1 : 0], out, nullptr, mask, B, H, W,
+                              a, nullptr, s1);
             if (r != hipSuccess) return r;
             U[k + 1] = out;
+        }
+        if (keep_v) {
+            const StepArgs a = make_args(p->sigma, R, p->tau, p->lambda, 0, model_of_flags(p->flags));
+            hipError_t r = launch_blur(R, U[n - 1], V + (size_t)(n - 1) * N, B, H, W, a, s1);
+            if (r != hipSuccess) return r;
         }
         return hipEventRecord(rec[m & 1], s1);
     };
@@ -1192,6 +1168,7 @@ extern "C" int eed4_backward(const float *ckpt, const uint8_t *mask, const float
         const std::vector<const float *> &U = Ur[m & 1];
         for (int k = n - 1; k >= 0 && rc2 == EED4_OK; --k) {
             t.u = U[k];
+            t.v = Vset[m & 1] + (size_t)k * N;
             t.an = an;
             t.ac = ac;
             t.ap = ap;

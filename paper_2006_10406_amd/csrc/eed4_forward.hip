@@ -48,13 +48,15 @@ __global__ __launch_bounds__(256) void step_kernel(const float *ucur, const floa
 }
 
 // Fused step over wave strips.  GEN selects the tensor variant at run time
-// (StepArgs::model); without it the kernel is the FOEED tensor.
-template <int R, bool RES, int ROWS, int CPL, bool GEN>
+// (StepArgs::model); without it the kernel is the FOEED tensor.  VST also
+// writes the presmoothed image K_sigma * u^k (into vout).
+template <int R, bool RES, int ROWS, int CPL, bool GEN, bool VST = false>
 __device__ __forceinline__ void strip_kernel_body(const float *ucur, const float *uprev,
                                                   float *uout, const float *ref,
                                                   const uint8_t *__restrict__ mask, int H, int W,
                                                   int nstrip, int per_img, int nitems,
-                                                  const StepArgs &a, double *partials)
+                                                  const StepArgs &a, double *partials,
+                                                  float *vout = nullptr)
 {
     using G = StripGeo<R, ROWS, CPL>;
     __shared__ float lds[4 * G::LDS];
@@ -71,6 +73,7 @@ __device__ __forceinline__ void strip_kernel_body(const float *ucur, const float
     s.uprev = uprev + off;
     s.uout = uout + off;
     s.ref = RES ? ref + off : nullptr;
+    s.vout = VST ? vout + off : nullptr;
     s.mask = mask + off;
     s.H = H;
     s.W = W;
@@ -80,8 +83,8 @@ __device__ __forceinline__ void strip_kernel_body(const float *ucur, const float
     s.alpha = a.alpha;
     s.il2q = 0.25f * a.inv_lam2;
     s.model = a.model;
-    strip_step<R, RES, ROWS, CPL, GEN>(lds + wave * G::LDS, s, a.w,
-                                       RES ? partials + 2 * (size_t)item : nullptr);
+    strip_step<R, RES, ROWS, CPL, GEN, VST>(lds + wave * G::LDS, s, a.w,
+                                            RES ? partials + 2 * (size_t)item : nullptr);
 }
 
 template <int R, bool RES, int ROWS, int CPL>
@@ -106,6 +109,64 @@ __global__ __launch_bounds__(256) void strip_model_kernel(const float *ucur, con
 {
     strip_kernel_body<R, RES, 28, 1, true>(ucur, uprev, uout, ref, mask, H, W, nstrip, per_img,
                                            nitems, a, partials);
+}
+
+// The step of the adjoint's forward recompute: u^{k+1} as strip_kernel (or
+// strip_model_kernel when GEN) computes it, and K_sigma * u^k for the reverse
+// step.
+template <int R, int ROWS, bool GEN>
+__global__ __launch_bounds__(256) void strip_keepv_kernel(const float *ucur, const float *uprev,
+                                                          float *uout, float *vout,
+                                                          const uint8_t *__restrict__ mask, int H,
+                                                          int W, int nstrip, int per_img,
+                                                          int nitems, StepArgs a)
+{
+    strip_kernel_body<R, false, ROWS, 1, GEN, true>(ucur, uprev, uout, nullptr, mask, H, W, nstrip,
+                                                    per_img, nitems, a, nullptr, vout);
+}
+
+// v = K_sigma * u on the mirror-extended image (the presmoothing of Sec. 2.2)
+// over 64 x 16 tiles: the same taps in the same order as the x and y passes of
+// the fused step, so v is bitwise the one a step from u computes.
+constexpr int kBlurTW = 64, kBlurTH = 16;
+template <int R>
+__global__ __launch_bounds__(256) void blur_kernel(const float *u_all, float *v_all, int H, int W,
+                                                   int nbx, int tiles_per_img, StepArgs a)
+{
+    constexpr int TW = kBlurTW, TH = kBlurTH, SH = TH + 2 * R, SWu = TW + 2 * R;
+    __shared__ float su[SH * SWu];
+    __shared__ float sx[SH * TW];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int b = tile / tiles_per_img;
+    const int t = tile - b * tiles_per_img;
+    const int y0 = (t / nbx) * TH, x0 = (t - (t / nbx) * nbx) * TW;
+    const float *u = u_all + (size_t)b * H * W;
+    float *v = v_all + (size_t)b * H * W;
+    for (int k = threadIdx.x; k < SH * SWu; k += 256) {
+        const int rr = k / SWu, cc = k - rr * SWu;
+        const int y = mirror_reflect(y0 - R + rr, H), x = mirror_reflect(x0 - R + cc, W);
+        su[k] = u[(size_t)y * W + x];
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < SH * TW; k += 256) {
+        const int rr = k / TW, c = k - rr * TW;
+        const float *row = su + rr * SWu + c;
+        float acc = a.w[0] * row[0];
+#pragma unroll
+        for (int j = 1; j <= 2 * R; ++j) acc = fmaf(a.w[j], row[j], acc);
+        sx[k] = acc;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < TH * TW; k += 256) {
+        const int r = k / TW, c = k - r * TW;
+        const int y = y0 + r, x = x0 + c;
+        if (y >= H || x >= W) continue;
+        const float *colp = sx + r * TW + c;
+        float acc = a.w[0] * colp[0];
+#pragma unroll
+        for (int j = 1; j <= 2 * R; ++j) acc = fmaf(a.w[j], colp[j * TW], acc);
+        v[(size_t)y * W + x] = acc;
+    }
 }
 
 // sums[b] = fixed-order sum of the residual partials of image b's tiles.
@@ -214,6 +275,60 @@ static hipError_t launch_strip_t(const float *ucur, const float *uprev, float *u
     return hipGetLastError();
 }
 
+template <int R, int ROWS, bool GEN>
+static hipError_t launch_keepv_t(const float *ucur, const float *uprev, float *uout, float *vout,
+                                 const uint8_t *mask, int B, int H, int W, const StepArgs &a,
+                                 hipStream_t s)
+{
+    using G = StripGeo<R, ROWS, 1>;
+    const int nstrip = (W + G::SW - 1) / G::SW;
+    const int per_img = nstrip * ((H + G::OH - 1) / G::OH);
+    const long long nitems = (long long)per_img * B;
+    const long long nblk = (nitems + 3) / 4;
+    if (nitems <= 0 || nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((strip_keepv_kernel<R, ROWS, GEN>), dim3((unsigned)nblk), dim3(256), 0, s,
+                       ucur, uprev, uout, vout, mask, H, W, nstrip, per_img, (int)nitems, a);
+    return hipGetLastError();
+}
+
+// Strip height of the keep-v step for a forward step shape: tensor variants
+// run 28-row strips; FOEED keeps the height of a strip shape (wide shapes map
+// to their height) and runs 8-row strips in place of a tile shape (small
+// images, where tiles win).
+static int keepv_rows(int shape, int model)
+{
+    if (model != 0) return 28;
+    switch (shape) {
+    case kShapeStrip: case kShapeStripTall: case kShapeStripWide: return 64;
+    case kShapeStripShort: case kShapeStripWideShort: return 28;
+    default: return 8;
+    }
+}
+
+template <int R>
+static hipError_t launch_keepv_r(int shape, const float *ucur, const float *uprev, float *uout,
+                                 float *vout, const uint8_t *mask, int B, int H, int W,
+                                 const StepArgs &a, hipStream_t s)
+{
+    const int rows = keepv_rows(shape, a.model);
+    if (a.model != 0) return launch_keepv_t<R, 28, true>(ucur, uprev, uout, vout, mask, B, H, W, a, s);
+    if (rows == 64) return launch_keepv_t<R, 64, false>(ucur, uprev, uout, vout, mask, B, H, W, a, s);
+    if (rows == 28) return launch_keepv_t<R, 28, false>(ucur, uprev, uout, vout, mask, B, H, W, a, s);
+    return launch_keepv_t<R, 8, false>(ucur, uprev, uout, vout, mask, B, H, W, a, s);
+}
+
+template <int R>
+static hipError_t launch_blur_r(const float *u, float *v, int B, int H, int W, const StepArgs &a,
+                                hipStream_t s)
+{
+    const int nbx = (W + kBlurTW - 1) / kBlurTW, nby = (H + kBlurTH - 1) / kBlurTH;
+    const long long ntiles = (long long)nbx * nby * B;
+    if (ntiles <= 0 || ntiles > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((blur_kernel<R>), dim3((unsigned)ntiles), dim3(256), 0, s, u, v, H, W, nbx,
+                       nbx * nby, a);
+    return hipGetLastError();
+}
+
 template <int R, int TW, int TH>
 static hipError_t launch_step_t(const float *ucur, const float *uprev, float *uout,
                                 const float *ref, const uint8_t *mask, int B, int H, int W,
@@ -261,6 +376,32 @@ hipError_t launch_step(int R, int shape, const float *ucur, const float *uprev, 
     switch (R) {
 #define EED4_CASE(r) \
     case r: return launch_step_r<r>(shape, ucur, uprev, uout, ref, mask, B, H, W, a, partials, s);
+        EED4_CASE(0) EED4_CASE(1) EED4_CASE(2) EED4_CASE(3) EED4_CASE(4)
+        EED4_CASE(5) EED4_CASE(6) EED4_CASE(7) EED4_CASE(8)
+#undef EED4_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_step_keepv(int R, int shape, const float *ucur, const float *uprev,
+                             float *uout, float *vout, const uint8_t *mask, int B, int H, int W,
+                             const StepArgs &a, hipStream_t s)
+{
+    switch (R) {
+#define EED4_CASE(r) \
+    case r: return launch_keepv_r<r>(shape, ucur, uprev, uout, vout, mask, B, H, W, a, s);
+        EED4_CASE(0) EED4_CASE(1) EED4_CASE(2) EED4_CASE(3) EED4_CASE(4)
+        EED4_CASE(5) EED4_CASE(6) EED4_CASE(7) EED4_CASE(8)
+#undef EED4_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_blur(int R, const float *u, float *v, int B, int H, int W, const StepArgs &a,
+                       hipStream_t s)
+{
+    switch (R) {
+#define EED4_CASE(r) case r: return launch_blur_r<r>(u, v, B, H, W, a, s);
         EED4_CASE(0) EED4_CASE(1) EED4_CASE(2) EED4_CASE(3) EED4_CASE(4)
         EED4_CASE(5) EED4_CASE(6) EED4_CASE(7) EED4_CASE(8)
 #undef EED4_CASE

@@ -67,6 +67,14 @@ hipError_t launch_hold(float *u, const uint8_t *mask, const float *known, size_t
 hipError_t launch_step(int R, int shape, const float *ucur, const float *uprev, float *uout,
                        const float *ref, const uint8_t *mask, int B, int H, int W,
                        const StepArgs &a, double *partials, hipStream_t s);
+// A step of the adjoint's forward recompute on strips (the height follows the
+// forward shape), which also writes K_sigma * u^k into vout.
+hipError_t launch_step_keepv(int R, int shape, const float *ucur, const float *uprev,
+                             float *uout, float *vout, const uint8_t *mask, int B, int H, int W,
+                             const StepArgs &a, hipStream_t s);
+// v = K_sigma * u, bitwise as a step from u computes it.
+hipError_t launch_blur(int R, const float *u, float *v, int B, int H, int W, const StepArgs &a,
+                       hipStream_t s);
 hipError_t launch_reduce(const double *partials, int tiles_per_img, int B, double *sums,
                          hipStream_t s);
 int tiles_per_image(int shape, int R, int H, int W);  // residual partials per image

@@ -14,7 +14,9 @@
 //       from the LDS ring (Sec. 3.3 stencils, sign-corrected u_xy) and
 //       T = D : H;
 //   S4  at row o = g-1: outer differences of T (eq. genModel), explicit step,
-//       FSI extrapolation (Sec. 3.3), Dirichlet hold; optional FP64 residual.
+//       FSI extrapolation (Sec. 3.3), Dirichlet hold; optional FP64 residual;
+//       optionally also the presmoothed image v = K_sigma * u^k at row o (the
+//       adjoint's recompute keeps it for the reverse step).
 // Horizontal neighbours inside a lane are its own registers; across lanes
 // they come from DPP wave shifts.  Outputs are the NL-4 columns X0 ..
 // X0+NL-5.  Every intermediate lives on the mirror-extended image, so P stays
@@ -91,6 +93,7 @@ struct StripArgs {
     const float *ucur, *uprev;
     float *uout;
     const float *ref;           // cycle start for the residual (RES variant only)
+    float *vout;                // K_sigma * u^k at the output pixels (VST variant only)
     const uint8_t *mask;
     int H, W, X0, Y0;
     float tau, alpha, il2q;     // il2q = 1 / (4 lambda^2)
@@ -190,7 +193,7 @@ __device__ __forceinline__ float right_of(const float (&x)[CPL], int q)
 // covering nb = min(H - b0, NROW) rows, so a row offset is one 32-bit scalar
 // (the library keeps NROW * W * 4 below 2^31) and the per-lane column offsets
 // stay fixed for the whole strip.
-template <int R, bool RES, int ROWS = 64, int CPL = 1, bool GEN = false>
+template <int R, bool RES, int ROWS = 64, int CPL = 1, bool GEN = false, bool VST = false>
 __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
                                            const float (&w)[2 * kRMax + 1], double *partial)
 {
@@ -210,6 +213,8 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
     const __amdgpu_buffer_rsrc_t rs_m = buffer_rsrc(s.mask + base, (unsigned)nb * (unsigned)W);
     __amdgpu_buffer_rsrc_t rs_r = rs_p;
     if constexpr (RES) rs_r = buffer_rsrc(s.ref + base, (unsigned)nb * W4);
+    __amdgpu_buffer_rsrc_t rs_v = rs_o;
+    if constexpr (VST) rs_v = buffer_rsrc(s.vout + base, (unsigned)nb * W4);
 
     // Staged columns (fixed for the whole strip): staged column j is image
     // column X0-2-R+j.  Lane l stages j = CPL l + q (q < CPL), and the 2R
@@ -336,9 +341,10 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
 
             // ---- S3: gradient, tensor, Hessian, contraction at row g = i - R - 1 ----
             // (the first rows of the loop produce values that only feed unstored rows)
-            float txx[CPL], tyy[CPL], txy[CPL], uc[CPL];
+            float txx[CPL], tyy[CPL], txy[CPL], uc[CPL], vo[CPL];
 #pragma unroll
             for (int q = 0; q < CPL; ++q) {
+                vo[q] = v_m2[q];                                              // v at row g - 1
                 const float gxs = right_of(v_m1, q) - left_of(v_m1, q);      // 2 gx
                 const float gys = v[q] - v_m2[q];                             // 2 gy
                 // column q of this lane is staged column CPL l + q + R; rows g-1, g, g+1
@@ -387,6 +393,9 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
                         n2 = fma(du, du, n2);
                     }
                     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(un), rs_o, vo4[q], ro, 0);
+                    if constexpr (VST)
+                        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(vo[q]), rs_v, vo4[q],
+                                                              ro, 0);
                 }
             }
 #pragma unroll
