@@ -218,7 +218,9 @@ int eed4_fsi_step(const float *ucur, const float *uprev, float *uout,
 
 /* Adjoint of eed4_inpaint run for exactly M cycles with tol == 0 (the FSI
  * evolution differentiated by hand; the paper gives the forward scheme only).
- * Each cycle is recomputed from its checkpoint, then reversed step by step;
+ * Each cycle is recomputed from its checkpoint (the states and, for the strip
+ * reverse step, their presmoothed images: 2n - 1 planes of B x H x W floats
+ * per cycle, two cycles' worth in the workspace), then reversed step by step;
  * the recompute of cycle m-1 runs on a library-owned stream (one per device,
  * default priority) while cycle m is reversed on `stream`, ordered by events,
  * and `stream` waits for all of it: work on `stream` after the call sees
