@@ -52,7 +52,9 @@ def compare(b, ck, gk, gi, gl, lam, sigma, tau, n, gu, label):
 
 @pytest.mark.parametrize("H,W,sigma,lam,n,M", [
     (40, 52, 1.0, 0.05, 5, 3), (67, 45, 1.5, 0.03, 4, 2), (33, 70, 2.0, 0.02, 3, 2),
-    (20, 17, 0.0, 0.1, 6, 2), (9, 130, 2.6, 0.05, 2, 2), (70, 66, 0.5, 0.04, 1, 3)])
+    (20, 17, 0.0, 0.1, 6, 2), (9, 130, 2.6, 0.05, 2, 2), (70, 66, 0.5, 0.04, 1, 3),
+    # many cycles: the recompute alternates its two buffer sets across odd and even counts
+    (30, 41, 1.0, 0.05, 3, 19), (26, 33, 1.5, 0.03, 2, 8)])
 def test_adjoint_matches_oracle(H, W, sigma, lam, n, M):
     announce(f"adjoint {H}x{W} sigma={sigma} n={n} M={M}")
     b = {k: np.stack([make_problem(H, W, 4, True, 0.01, 0.08, 900 + i + H)[k] for i in range(2)])
