@@ -85,37 +85,43 @@ _L = None
 def lib():
     global _L
     if _L is None:
-        if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
-                              "(python -c 'import __graft_entry__ as g; g.build()')")
-        L = ctypes.CDLL(LIB_PATH)
-        vp, sz, i, f = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_float
-        pp = ctypes.POINTER(eed4_params)
-        L.eed4_radius.restype = i
-        L.eed4_radius.argtypes = [f]
-        L.eed4_workspace_size.restype = sz
-        L.eed4_workspace_size.argtypes = [i, i, i, i, pp]
-        L.eed4_inpaint.restype = i
-        L.eed4_inpaint.argtypes = [vp, vp, vp, i, i, i, pp, vp, vp, sz, vp,
-                                   ctypes.POINTER(eed4_stats), vp]
-        L.eed4_fsi_cycle.restype = i
-        L.eed4_fsi_cycle.argtypes = [vp, vp, vp, i, i, i, pp, vp, sz, vp, vp]
-        L.eed4_fsi_cycle_static.restype = i
-        L.eed4_fsi_cycle_static.argtypes = [vp, vp, vp, i, i, i, pp, vp, vp]
-        L.eed4_fsi_step.restype = i
-        L.eed4_fsi_step.argtypes = [vp, vp, vp, vp, i, i, i, pp, i, vp]
-        L.eed4_backward.restype = i
-        L.eed4_backward.argtypes = [vp, vp, vp, i, i, i, pp, i, vp, vp, vp, vp, vp, sz, vp]
-        L.eed4_batched_workspace_size.restype = sz
-        L.eed4_batched_workspace_size.argtypes = [ctypes.POINTER(eed4_image), i, pp]
-        L.eed4_inpaint_batched.restype = i
-        L.eed4_inpaint_batched.argtypes = [ctypes.POINTER(eed4_image), i, pp, vp, sz, vp,
-                                           ctypes.POINTER(eed4_stats)]
-        L.eed4_autotune_batched.restype = i
-        L.eed4_autotune_batched.argtypes = [ctypes.POINTER(eed4_image), i, pp, vp, sz, vp]
-        L.eed4_step_shape.restype = i
-        L.eed4_step_shape.argtypes = [i, i, i, pp]
-        L.eed4_strerror.restype = ctypes.c_char_p
-        L.eed4_strerror.argtypes = [i]
-        _L = L
+        _L = load_library(LIB_PATH)
     return _L
+
+
+def load_library(path):
+    """ctypes handle of a build of the library at path, with the signatures of
+    include/eed4.h (the binding uses the one at LIB_PATH)."""
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build the HIP library first "
+                          "(python -c 'import __graft_entry__ as g; g.build()')")
+    L = ctypes.CDLL(path)
+    vp, sz, i, f = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_float
+    pp = ctypes.POINTER(eed4_params)
+    L.eed4_radius.restype = i
+    L.eed4_radius.argtypes = [f]
+    L.eed4_workspace_size.restype = sz
+    L.eed4_workspace_size.argtypes = [i, i, i, i, pp]
+    L.eed4_inpaint.restype = i
+    L.eed4_inpaint.argtypes = [vp, vp, vp, i, i, i, pp, vp, vp, sz, vp,
+                               ctypes.POINTER(eed4_stats), vp]
+    L.eed4_fsi_cycle.restype = i
+    L.eed4_fsi_cycle.argtypes = [vp, vp, vp, i, i, i, pp, vp, sz, vp, vp]
+    L.eed4_fsi_cycle_static.restype = i
+    L.eed4_fsi_cycle_static.argtypes = [vp, vp, vp, i, i, i, pp, vp, vp]
+    L.eed4_fsi_step.restype = i
+    L.eed4_fsi_step.argtypes = [vp, vp, vp, vp, i, i, i, pp, i, vp]
+    L.eed4_backward.restype = i
+    L.eed4_backward.argtypes = [vp, vp, vp, i, i, i, pp, i, vp, vp, vp, vp, vp, sz, vp]
+    L.eed4_batched_workspace_size.restype = sz
+    L.eed4_batched_workspace_size.argtypes = [ctypes.POINTER(eed4_image), i, pp]
+    L.eed4_inpaint_batched.restype = i
+    L.eed4_inpaint_batched.argtypes = [ctypes.POINTER(eed4_image), i, pp, vp, sz, vp,
+                                       ctypes.POINTER(eed4_stats)]
+    L.eed4_autotune_batched.restype = i
+    L.eed4_autotune_batched.argtypes = [ctypes.POINTER(eed4_image), i, pp, vp, sz, vp]
+    L.eed4_step_shape.restype = i
+    L.eed4_step_shape.argtypes = [i, i, i, pp]
+    L.eed4_strerror.restype = ctypes.c_char_p
+    L.eed4_strerror.argtypes = [i]
+    return L

@@ -3,6 +3,10 @@
 Every ``csrc/*.hip`` file is compiled to an object under ``_build/`` and the
 objects are linked into ``paper_2006_10406_amd/lib/libeed4.so``.  Packed FP32
 instructions are disabled for all device code.
+
+``build_sentinel()`` builds the same sources with ``EED4_LDS_SENTINEL=1`` into
+``lib/libeed4_sentinel.so``: a debug library whose stencil kernels fill their
+LDS with NaN before each stage, for the halo-coverage tests only.
 """
 from __future__ import annotations
 
@@ -19,6 +23,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libeed4.so")
+SENTINEL_LIB = os.path.join(LIBDIR, "libeed4_sentinel.so")
 ARCH = "gfx950"
 
 
@@ -36,9 +41,9 @@ def compile_flags():
             "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [hipcc()] + compile_flags() + ["-c", src, "-o", obj]
+def _compile(src: str, verbose: bool, objdir: str = BUILD, defines=()) -> str:
+    obj = os.path.join(objdir, os.path.basename(src) + ".o")
+    cmd = [hipcc()] + compile_flags() + [f"-D{d}" for d in defines] + ["-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -51,21 +56,33 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def _build_lib(out: str, objdir: str, defines, verbose: bool, jobs: int) -> str:
+    os.makedirs(objdir, exist_ok=True)
     os.makedirs(LIBDIR, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, verbose, objdir, defines), srcs))
+    tmp = out + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
+
+
+def build(verbose: bool = False, jobs: int = 4) -> str:
+    return _build_lib(LIB, BUILD, (), verbose, jobs)
+
+
+def build_sentinel(verbose: bool = False, jobs: int = 4) -> str:
+    return _build_lib(SENTINEL_LIB, os.path.join(BUILD, "sentinel"), ("EED4_LDS_SENTINEL=1",),
+                      verbose, jobs)
 
 
 if __name__ == "__main__":
     build(verbose="-v" in sys.argv)
     print(LIB)
+    if "--sentinel" in sys.argv:
+        build_sentinel(verbose="-v" in sys.argv)
+        print(SENTINEL_LIB)

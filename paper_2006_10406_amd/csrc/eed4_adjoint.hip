@@ -203,6 +203,7 @@ __global__ __launch_bounds__(256) void adjoint_a_kernel(const float *u_all, cons
     const float *u = u_all + off, *an = an_all + off;
     const uint8_t *mask = mask_all + off;
     const int tid = threadIdx.x, gx0 = tx * TW, gy0 = ty * TH;
+    if constexpr (kLdsSentinel) sentinel_fill_block(smem, G::SMEM);
 
     // ---- load u (halo R+2) and r (halo 2) ----
     for (int i = tid; i < G::UH * G::UWr; i += kThreads) {
@@ -271,6 +272,7 @@ __global__ __launch_bounds__(256) void adjoint_a_kernel(const float *u_all, cons
         }
     }
     __syncthreads();
+    if constexpr (kLdsSentinel) sentinel_fill_block(sT, G::NT);
 #pragma unroll
     for (int k = 0; k < G::NPT; ++k) {
         int p = tid + k * kThreads;
@@ -340,6 +342,7 @@ __global__ __launch_bounds__(256) void adjoint_b_kernel(const float *qx_all, con
     const int ty = t / nbx, tx = t - ty * nbx;
     const size_t off = (size_t)bimg * H * W;
     const int tid = threadIdx.x, gx0 = tx * TW, gy0 = ty * TH;
+    if constexpr (kLdsSentinel) sentinel_fill_block(smem, G::SMEM);
 
     for (int i = tid; i < G::NQ; i += kThreads) {
         int r = i / G::QW, c = i - r * G::QW;
@@ -442,6 +445,7 @@ __device__ __forceinline__ void adjoint_strip_step(float *lds, const AdjStripArg
     const int lane = threadIdx.x & 63;
     const int H = s.H, W = s.W;
     const unsigned W4 = 4u * (unsigned)W;
+    if constexpr (kLdsSentinel) sentinel_fill_wave(lds, G::LDS);
 
     // resources based at the lowest row a needed value comes from (as in
     // the forward strip)

@@ -142,6 +142,10 @@ __global__ __launch_bounds__(256) void blur_kernel(const float *u_all, float *v_
     const int y0 = (t / nbx) * TH, x0 = (t - (t / nbx) * nbx) * TW;
     const float *u = u_all + (size_t)b * H * W;
     float *v = v_all + (size_t)b * H * W;
+    if constexpr (kLdsSentinel) {
+        sentinel_fill_block(su, SH * SWu);
+        sentinel_fill_block(sx, SH * TW);
+    }
     for (int k = threadIdx.x; k < SH * SWu; k += 256) {
         const int rr = k / SWu, cc = k - rr * SWu;
         const int y = mirror_reflect(y0 - R + rr, H), x = mirror_reflect(x0 - R + cc, W);

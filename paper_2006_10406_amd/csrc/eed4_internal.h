@@ -11,6 +11,32 @@ namespace eed4 {
 constexpr int kRMax = 8;        // largest Gaussian radius (sigma <= 8/3)
 constexpr int kThreads = 256;   // threads per workgroup of the tile kernels
 
+// Debug build (compiled with EED4_LDS_SENTINEL=1): every stencil kernel fills
+// its LDS with NaN before each stage that writes it, so a read of a slot the
+// stage did not write (an undersized halo, a missing barrier) turns the outputs
+// it feeds into NaN or changes them.  Off (and compiled out) in the library.
+#ifndef EED4_LDS_SENTINEL
+#define EED4_LDS_SENTINEL 0
+#endif
+constexpr bool kLdsSentinel = EED4_LDS_SENTINEL != 0;
+
+// NaN into p[0 .. n) by the whole workgroup, then a workgroup barrier.
+__device__ __forceinline__ void sentinel_fill_block(float *p, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = __builtin_nanf("");
+    __syncthreads();
+}
+
+// NaN into p[0 .. n) by one wave (its own LDS region); the wave's later LDS
+// accesses stay after these stores.
+__device__ __forceinline__ void sentinel_fill_wave(float *p, int n)
+{
+    for (int i = threadIdx.x & 63; i < n; i += 64) p[i] = __builtin_nanf("");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
 // Per-launch constants of one inner FSI step.
 struct StepArgs {
     float w[2 * kRMax + 1];  // sampled Gaussian, w[j + R], j = -R..R, sums to 1

@@ -202,6 +202,7 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
     const int lane = threadIdx.x & 63;
     const int H = s.H, W = s.W;
     const unsigned W4 = 4u * (unsigned)W;
+    if constexpr (kLdsSentinel) sentinel_fill_wave(ring, G::LDS);
 
     const int ybase = s.Y0 - G::h;                            // image row of stream row 0
     const int b0 = ybase > 0 ? ybase : 0;

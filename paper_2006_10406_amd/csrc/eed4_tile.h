@@ -103,6 +103,7 @@ __device__ __forceinline__ void step_tile(float *smem, const float *ucur, const 
     float *sT = smem;  // [3][PH][PW], written after sU and sX are dead
     const int tid = threadIdx.x;
     const int gx0 = tx * TW, gy0 = ty * TH;
+    if constexpr (kLdsSentinel) sentinel_fill_block(smem, G::SMEM);
 
     // The pointwise operands of this thread's outputs (stage E: rows rr,
     // rr + RPP, ... of column c) are loaded first, so that their memory
@@ -215,6 +216,7 @@ __device__ __forceinline__ void step_tile(float *smem, const float *ucur, const 
         }
     }
     __syncthreads();
+    if constexpr (kLdsSentinel) sentinel_fill_block(sT, G::NT);
 #pragma unroll
     for (int k = 0; k < G::NPT; ++k) {
         int p = tid + k * kThreads;
