@@ -6,7 +6,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "lib", "libeed4.so")
+# EED4_LIBRARY names another build of the library (the sanitizer tests use it)
+LIB_PATH = os.environ.get("EED4_LIBRARY") or os.path.join(HERE, "lib", "libeed4.so")
 
 EED4_OK = 0
 EED4_EINVAL = -1
