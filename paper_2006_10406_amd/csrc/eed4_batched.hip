@@ -118,21 +118,22 @@ __global__ __launch_bounds__(256) void bstrip_model_kernel(const BImage *imgs, c
 
 // Workgroup-tile shapes: workgroup g takes tiles g, g + G, g + 2 G, ...
 template <int R, int TW, int TH>
-__global__ __launch_bounds__(256) void btile_kernel(const BImage *imgs, const BItem *queue,
-                                                    const int *qlen_p, int sc, int sp, int so,
-                                                    int residual, StepArgs a, double *partials)
+__global__ __launch_bounds__(tile_threads(TW, TH)) void btile_kernel(
+    const BImage *imgs, const BItem *queue, const int *qlen_p, int sc, int sp, int so,
+    int residual, StepArgs a, double *partials)
 {
-    __shared__ __attribute__((aligned(16))) float smem[TileGeo<R, TW, TH>::SMEM];
+    constexpr int NTH = tile_threads(TW, TH);
+    __shared__ __attribute__((aligned(16))) float smem[TileGeo<R, TW, TH, NTH>::SMEM];
     const int qlen = *qlen_p;
     for (int it = xcd_tile(blockIdx.x, gridDim.x); it < qlen; it += gridDim.x) {
         __syncthreads();           // the previous tile's last LDS reads are done
         const BItem t = queue[it];
         const BImage d = imgs[t.img];
-        step_tile<R, TW, TH>(smem, uni(pick(d, sc)), uni(pick(d, sp)), uni(pick(d, so)),
-                             residual ? uni(d.buf[0]) : nullptr, uni(d.mask), uni(d.H), uni(d.W),
-                             uni(t.iy), uni(t.ix), a.w, a.tau, a.alpha,
-                             0.25f * __int_as_float(uni(__float_as_int(d.inv_lam2))),
-                             residual ? partials + 2 * (size_t)uni(t.slot) : nullptr);
+        step_tile<R, TW, TH, NTH>(smem, uni(pick(d, sc)), uni(pick(d, sp)), uni(pick(d, so)),
+                                  residual ? uni(d.buf[0]) : nullptr, uni(d.mask), uni(d.H),
+                                  uni(d.W), uni(t.iy), uni(t.ix), a.w, a.tau, a.alpha,
+                                  0.25f * __int_as_float(uni(__float_as_int(d.inv_lam2))),
+                                  residual ? partials + 2 * (size_t)uni(t.slot) : nullptr);
     }
 }
 
@@ -212,9 +213,9 @@ static hipError_t launch_bstep_r(int shape, int grid, const BImage *imgs, const 
                                  const StepArgs &a, double *partials, hipStream_t s)
 {
     dim3 g(grid), b(256);
-#define EED4_BTILE(TW, TH)                                                                    \
-    hipLaunchKernelGGL((btile_kernel<R, TW, TH>), g, b, 0, s, imgs, queue, qlen, sc, sp, so, \
-                       res ? 1 : 0, a, partials)
+#define EED4_BTILE(TW, TH)                                                                   \
+    hipLaunchKernelGGL((btile_kernel<R, TW, TH>), g, dim3(tile_threads(TW, TH)), 0, s, imgs, \
+                       queue, qlen, sc, sp, so, res ? 1 : 0, a, partials)
 #define EED4_BSTRIP(ROWS, CPL)                                                           \
     if (res)                                                                             \
         hipLaunchKernelGGL((bstrip_kernel<R, ROWS, true, CPL>), g, b, 0, s, imgs, queue, \

@@ -30,21 +30,22 @@ __global__ __launch_bounds__(256) void hold_kernel(float *u, const uint8_t *__re
 }
 
 template <int R, int TW, int TH>
-__global__ __launch_bounds__(256) void step_kernel(const float *ucur, const float *uprev,
-                                                   float *uout, const float *ref,
-                                                   const uint8_t *__restrict__ mask, int H, int W,
-                                                   int nbx, int tiles_per_img, StepArgs a,
-                                                   double *partials)
+__global__ __launch_bounds__(tile_threads(TW, TH)) void step_kernel(
+    const float *ucur, const float *uprev, float *uout, const float *ref,
+    const uint8_t *__restrict__ mask, int H, int W, int nbx, int tiles_per_img, StepArgs a,
+    double *partials)
 {
-    __shared__ __attribute__((aligned(16))) float smem[TileGeo<R, TW, TH>::SMEM];
+    constexpr int NTH = tile_threads(TW, TH);
+    __shared__ __attribute__((aligned(16))) float smem[TileGeo<R, TW, TH, NTH>::SMEM];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int b = tile / tiles_per_img;
     const int t = tile - b * tiles_per_img;
     const int ty = t / nbx, tx = t - ty * nbx;
     const size_t off = (size_t)b * H * W;
-    step_tile<R, TW, TH>(smem, ucur + off, uprev + off, uout + off, ref ? ref + off : nullptr,
-                         mask + off, H, W, ty, tx, a.w, a.tau, a.alpha, 0.25f * a.inv_lam2,
-                         partials ? partials + 2 * (size_t)tile : nullptr);
+    step_tile<R, TW, TH, NTH>(smem, ucur + off, uprev + off, uout + off,
+                              ref ? ref + off : nullptr, mask + off, H, W, ty, tx, a.w, a.tau,
+                              a.alpha, 0.25f * a.inv_lam2,
+                              partials ? partials + 2 * (size_t)tile : nullptr);
 }
 
 // Fused step over wave strips.  GEN selects the tensor variant at run time
@@ -342,7 +343,8 @@ static hipError_t launch_step_t(const float *ucur, const float *uprev, float *uo
     const int tpi = nbx * nby;
     const long long ntiles = (long long)tpi * B;
     if (ntiles <= 0 || ntiles > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((step_kernel<R, TW, TH>), dim3((unsigned)ntiles), dim3(256), 0, s, ucur,
+    hipLaunchKernelGGL((step_kernel<R, TW, TH>), dim3((unsigned)ntiles), dim3(tile_threads(TW, TH)),
+                       0, s, ucur,
                        uprev, uout, ref, mask, H, W, nbx, tpi, a, partials);
     return hipGetLastError();
 }

@@ -1,6 +1,6 @@
 // Device code of one fused FOEED/FSI inner step on one output tile.
 //
-// One workgroup of 256 threads computes a TW x TH tile of u^{k+1} from u^k
+// One workgroup of NTH threads (256 unless given) computes a TW x TH tile of u^{k+1} from u^k
 // (read with a halo of R+2 pixels, R = Gaussian radius) and u^{k-1}:
 //   A  load u^k (tile + halo) into LDS; border tiles gather through the
 //      half-sample mirror, which realises the Neumann condition (Sec. 2.1)
@@ -30,9 +30,9 @@ __device__ __forceinline__ int mirror_index(int i, int n)
     return m < n ? m : p - 1 - m;
 }
 
-template <int R, int TW, int TH>
+template <int R, int TW, int TH, int NTH = kThreads>
 struct TileGeo {
-    static_assert(TW % 4 == 0 && kThreads % TW == 0, "tile width");
+    static_assert(TW % 4 == 0 && NTH % TW == 0, "tile width");
     static constexpr int h = R + 2;                       // input halo
     static constexpr int UH = TH + 2 * h;                 // rows of u in LDS
     static constexpr int UWr = TW + 2 * h;                // used columns of u
@@ -49,19 +49,20 @@ struct TileGeo {
     static constexpr int nyr()
     {
         int r = 4;
-        while (((VH + r - 1) / r) * XW > kThreads && r < VH) ++r;
+        while (((VH + r - 1) / r) * XW > NTH && r < VH) ++r;
         return r;
     }
     static constexpr int NYR = nyr();                     // rows per y-pass item
     static constexpr int NRUN = (VH + NYR - 1) / NYR;
-    static constexpr int NPT = (NP + kThreads - 1) / kThreads;
-    static constexpr int RPP = kThreads / TW;             // output rows per pass
+    static constexpr int NPT = (NP + NTH - 1) / NTH;
+    static constexpr int RPP = NTH / TW;                  // output rows per pass
     static_assert(TH % RPP == 0, "tile height");
     static_assert(UW * UH >= 0, "");
 };
 
 // Accumulates sum (un - ref)^2 and sum un^2 of the tile in FP64 and writes
 // them to out[0..1] (thread 0).  Fixed reduction order: deterministic.
+template <int NTH = kThreads>
 __device__ __forceinline__ void block_sum2(double d2, double n2, double *scratch, double *out)
 {
     for (int o = 32; o > 0; o >>= 1) {
@@ -77,7 +78,7 @@ __device__ __forceinline__ void block_sum2(double d2, double n2, double *scratch
     __syncthreads();
     if (threadIdx.x == 0) {
         double a = 0.0, b = 0.0;
-        for (int i = 0; i < kThreads / 64; ++i) {
+        for (int i = 0; i < NTH / 64; ++i) {
             a += scratch[2 * i];
             b += scratch[2 * i + 1];
         }
@@ -89,14 +90,14 @@ __device__ __forceinline__ void block_sum2(double d2, double n2, double *scratch
 // One tile.  ucur/uprev/uout/ref/mask point at the image (H x W).  ref, when
 // not null, is the cycle-start state for the residual (it may equal uout: each
 // pixel is read before it is written by the same thread).
-template <int R, int TW, int TH>
+template <int R, int TW, int TH, int NTH = kThreads>
 __device__ __forceinline__ void step_tile(float *smem, const float *ucur, const float *uprev,
                                           float *uout, const float *ref,
                                           const uint8_t *__restrict__ mask, int H, int W, int ty,
                                           int tx, const float (&w)[2 * kRMax + 1], float tau,
                                           float alpha, float il2q, double *partial)
 {
-    using G = TileGeo<R, TW, TH>;
+    using G = TileGeo<R, TW, TH, NTH>;
     float *sU = smem;
     float *sX = smem + G::NU;
     float *sV = smem + G::REGA;
@@ -134,12 +135,12 @@ __device__ __forceinline__ void step_tile(float *smem, const float *ucur, const 
         const int x0 = gx0 - G::h, y0 = gy0 - G::h;
         const bool inside = x0 >= 0 && y0 >= 0 && x0 + G::UWr <= W && y0 + G::UH <= H;
         if (inside) {
-            for (int i = tid; i < G::UH * G::UWr; i += kThreads) {
+            for (int i = tid; i < G::UH * G::UWr; i += NTH) {
                 int r = i / G::UWr, c = i - r * G::UWr;
                 sU[r * G::UW + c] = ucur[(size_t)(y0 + r) * W + (x0 + c)];
             }
         } else {
-            for (int i = tid; i < G::UH * G::UWr; i += kThreads) {
+            for (int i = tid; i < G::UH * G::UWr; i += NTH) {
                 int r = i / G::UWr, c = i - r * G::UWr;
                 int yy = mirror_index(y0 + r, H), xx = mirror_index(x0 + c, W);
                 sU[r * G::UW + c] = ucur[(size_t)yy * W + xx];
@@ -149,7 +150,7 @@ __device__ __forceinline__ void step_tile(float *smem, const float *ucur, const 
     __syncthreads();
 
     // ---- B: x pass, 4 outputs per item ----
-    for (int i = tid; i < G::UH * G::NQ; i += kThreads) {
+    for (int i = tid; i < G::UH * G::NQ; i += NTH) {
         int r = i / G::NQ, q = i - r * G::NQ;
         const float4 *src = reinterpret_cast<const float4 *>(sU + r * G::UW + 4 * q);
         float win[4 * G::NF4];
@@ -174,7 +175,7 @@ __device__ __forceinline__ void step_tile(float *smem, const float *ucur, const 
     __syncthreads();
 
     // ---- C: y pass, NYR outputs per item ----
-    for (int i = tid; i < G::NRUN * G::XW; i += kThreads) {
+    for (int i = tid; i < G::NRUN * G::XW; i += NTH) {
         int run = i / G::XW, c = i - run * G::XW;
         int r0 = run * G::NYR;
         float win[G::NYR + 2 * R];
@@ -197,7 +198,7 @@ __device__ __forceinline__ void step_tile(float *smem, const float *ucur, const 
     float txx[G::NPT], tyy[G::NPT], txy[G::NPT];
 #pragma unroll
     for (int k = 0; k < G::NPT; ++k) {
-        int p = tid + k * kThreads;
+        int p = tid + k * NTH;
         txx[k] = tyy[k] = txy[k] = 0.0f;
         if (p < G::NP) {
             int pr = p / G::PW, pc = p - pr * G::PW;
@@ -219,7 +220,7 @@ __device__ __forceinline__ void step_tile(float *smem, const float *ucur, const 
     if constexpr (kLdsSentinel) sentinel_fill_block(sT, G::NT);
 #pragma unroll
     for (int k = 0; k < G::NPT; ++k) {
-        int p = tid + k * kThreads;
+        int p = tid + k * NTH;
         if (p < G::NP) {
             sT[p] = txx[k];
             sT[G::NP + p] = tyy[k];
@@ -257,7 +258,7 @@ __device__ __forceinline__ void step_tile(float *smem, const float *ucur, const 
     }
     if (ref) {
         __syncthreads();
-        block_sum2(d2, n2, reinterpret_cast<double *>(smem), partial);
+        block_sum2<NTH>(d2, n2, reinterpret_cast<double *>(smem), partial);
     }
 }
 
