@@ -434,14 +434,18 @@ def workload_throughput(eed4, torch, names=("rgb512", "scratch512_thin", "scratc
     known = torch.from_numpy(pr["known"]).cuda()
     u0 = torch.from_numpy(pr["u_init"]).cuda()
     p = eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, wl.M, tol=wl.tol)
+    # warm-up: the same call (step-shape tuning, cycle graphs, the pinned residual buffer)
     u = u0.clone()
-    eed4.eed4_inpaint(u, mask, known, eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, 2))
-    u = u0.clone()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st, _ = eed4.eed4_inpaint(u, mask, known, p)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3
+    eed4.eed4_inpaint(u, mask, known, p)
+    times = []
+    for _ in range(3):
+        u = u0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, _ = eed4.eed4_inpaint(u, mask, known, p)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    ms = sorted(times)[1]                   # median of three runs
     res["single512_to_tol"] = {"cycles": st.cycles, "rel_residual": st.rel_residual,
                                "ms": round(ms, 2),
                                "mpix_updates_s": round(wl.H * wl.W * wl.n * st.cycles

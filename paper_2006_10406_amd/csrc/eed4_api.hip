@@ -240,7 +240,7 @@ int cycle_graph(const CycleJob &j, int nc, hipGraphExec_t *exec, bool *owned)
 }
 
 struct InpaintLayout {
-    size_t X, Y, T, partials, sums, sums2, hist, total;
+    size_t X, Y, T, partials, sums, hist, total;
 };
 
 // residual partials: enough for the largest per-image count of any kernel shape
@@ -265,9 +265,8 @@ InpaintLayout inpaint_layout(int op, int B, int H, int W, int R, int M)
     L.partials = o; o = align_up(o + sizeof(double) * 2 * tiles);
     L.sums = o; o = align_up(o + sizeof(double) * 2 * (size_t)B);
     if (op == EED4_OP_INPAINT) {
-        // the second state buffer and residual sums of the run to a tolerance
+        // the second state buffer of the run to a tolerance
         L.T = o; o = align_up(o + sizeof(float) * N);
-        L.sums2 = o; o = align_up(o + sizeof(double) * 2 * (size_t)B);
     }
     L.hist = o;
     if (op == EED4_OP_INPAINT) o = align_up(o + sizeof(double) * 2 * (size_t)B * M);
@@ -372,9 +371,12 @@ int check_ws(void *ws, size_t ws_bytes, size_t need)
     return EED4_OK;
 }
 
-// Pinned host memory of at least `bytes` for the residual read-backs of the
-// calling thread (asynchronous copies need page-locked memory).  Grows and is
-// kept for the thread's lifetime.
+// Pinned, coherent host memory of at least `bytes` for the residual sums of
+// the calling thread's runs to tolerance: the cycle's reduction kernel stores
+// them straight into it over the bus, so no copy sits in the stream between
+// two cycles.  Grows and is kept for the thread's lifetime (a cycle graph
+// captured on a buffer that was since replaced is never launched again: the
+// graph cache keys on the pointer).
 static double *pinned_sums(size_t bytes)
 {
     static thread_local double *buf = nullptr;
@@ -384,7 +386,7 @@ static double *pinned_sums(size_t bytes)
         buf = nullptr;
         cap = 0;
         void *q = nullptr;
-        if (hipHostMalloc(&q, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+        if (hipHostMalloc(&q, bytes, hipHostMallocCoherent) != hipSuccess) return nullptr;
         buf = (double *)q;
         cap = bytes;
     }
@@ -418,23 +420,31 @@ static void evaluate_residuals(const double *sums, int B, RunResult &r)
 // writes only the buffer that does not hold the accepted result; at the end
 // the result is copied into u when it lies in T.  That extra cycle also writes
 // its checkpoint slot (when it exists) and history slot, which the caller does
-// not read.
-static int run_to_tolerance(const CycleJob &j, float *T, double *sums2, const eed4_params *p,
+// not read.  Each cycle's reduction stores its residual sums straight into
+// slot m & 1 of a pinned host buffer, which the host reads once the event
+// recorded after the cycle has completed.
+static int run_to_tolerance(const CycleJob &j, float *T, const eed4_params *p,
                             float *ckpt, double *hist_dev, hipStream_t s, RunResult *out)
 {
     const int M = p->max_cycles, B = j.B;
     const size_t N = (size_t)B * j.H * j.W;
-    CycleJob job[2] = {j, j};
-    job[0].Out = T;                                   // even cycles: u -> T
-    job[1].S = T; job[1].Out = j.S; job[1].sums = sums2;   // odd cycles: T -> u
-    hipGraphExec_t exec[2] = {nullptr, nullptr};
-    bool own[2] = {false, false};
     int rc = EED4_OK;
     hipError_t e = hipSuccess;
+    // cycle m's sums land in slot m & 1 of the pinned buffer
+    double *host = pinned_sums(sizeof(double) * 4 * (size_t)B);
+    void *dev_host = nullptr;
+    if (!host) rc = hip_fail(hipErrorOutOfMemory, "pinned host buffer");
+    else if ((e = hipHostGetDevicePointer(&dev_host, host, 0)) != hipSuccess)
+        rc = hip_fail(e, "pinned host buffer");
+    CycleJob job[2] = {j, j};
+    job[0].Out = T;                                   // even cycles: u -> T
+    job[1].S = T; job[1].Out = j.S;                   // odd cycles: T -> u
+    job[0].sums = (double *)dev_host;
+    job[1].sums = (double *)dev_host + 2 * (size_t)B;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    bool own[2] = {false, false};
     for (int i = 0; i < 2 && rc == EED4_OK && !(p->flags & EED4_NO_GRAPH); ++i)
         rc = cycle_graph(job[i], 1, &exec[i], &own[i]);
-    double *host = rc == EED4_OK ? pinned_sums(sizeof(double) * 4 * (size_t)B) : nullptr;
-    if (rc == EED4_OK && !host) rc = hip_fail(hipErrorOutOfMemory, "pinned host buffer");
     hipEvent_t ev[2] = {nullptr, nullptr};
     for (int i = 0; i < 2 && rc == EED4_OK; ++i) {
         e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
@@ -456,12 +466,10 @@ static int run_to_tolerance(const CycleJob &j, float *T, double *sums2, const ee
         }
         if (hist_dev) {
             e = hipMemcpyAsync(hist_dev + 2 * (size_t)B * m, c.sums, sizeof(double) * 2 * B,
-                               hipMemcpyDeviceToDevice, s);
+                               hipMemcpyDefault, s);
             if (e != hipSuccess) return hip_fail(e, "history copy");
         }
-        e = hipMemcpyAsync(host + 2 * (size_t)B * (m & 1), c.sums, sizeof(double) * 2 * B,
-                           hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipEventRecord(ev[m & 1], s);
+        e = hipEventRecord(ev[m & 1], s);
         return e == hipSuccess ? (int)EED4_OK : hip_fail(e, "residual read-back");
     };
     int m = 0;
@@ -635,8 +643,8 @@ int eed4_inpaint(float *u, const uint8_t *mask, const float *known, int B, int H
 
     RunResult res;
     if (p->tol > 0.0f && M > 1) {
-        rc = run_to_tolerance(j, (float *)(base + L.T), (double *)(base + L.sums2), p, ckpt,
-                              hist ? hist_dev : nullptr, s, &res);
+        rc = run_to_tolerance(j, (float *)(base + L.T), p, ckpt, hist ? hist_dev : nullptr, s,
+                              &res);
     } else {
         rc = run_fixed(j, M, p, ckpt, hist ? hist_dev : nullptr, s, &res);
     }
