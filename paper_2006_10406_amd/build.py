@@ -24,6 +24,8 @@ BUILD = os.path.join(HERE, "_build")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libeed4.so")
 SENTINEL_LIB = os.path.join(LIBDIR, "libeed4_sentinel.so")
+# roctx ranges and marks of the host code (rocprofiler-sdk)
+LINK_LIBS = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
 ARCH = "gfx950"
 
 
@@ -63,7 +65,7 @@ def _build_lib(out: str, objdir: str, defines, verbose: bool, jobs: int) -> str:
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose, objdir, defines), srcs))
     tmp = out + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + LINK_LIBS
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -1022,6 +1022,7 @@ static std::string adjoint_tune_key(int R, int B, int H, int W)
 // on the caller's data (t holds real buffers; what it writes is scratch).
 static int adjoint_shape(const eed4_params *p, RevStep t, hipStream_t s, int *shape)
 {
+    TraceRange range("eed4 reverse-step shape %dx%dx%d", t.B, t.H, t.W);
     if (model_of_flags(p->flags) != 0) { *shape = kShapeStripShort; return EED4_OK; }
     const int forced = (p->flags >> 8) & 0xff;
     if (forced >= 1 && forced <= kNumShapes) { *shape = forced - 1; return EED4_OK; }
@@ -1058,6 +1059,7 @@ extern "C" int eed4_backward(const float *ckpt, const uint8_t *mask, const float
                              float *grad_known, float *grad_init, float *grad_lambda, void *ws,
                              size_t ws_bytes, void *stream)
 {
+    TraceRange range("eed4_backward %dx%dx%d, %d cycles of %d", B, H, W, M, p ? p->cycle_len : 0);
     int rc = check_params(p, B, H, W);
     if (rc != EED4_OK) return rc;
     if (!ckpt || !mask || !known || !grad_u || !grad_known || !grad_init || !grad_lambda || M < 1)
@@ -1133,6 +1135,7 @@ extern "C" int eed4_backward(const float *ckpt, const uint8_t *mask, const float
     // K_sigma * u^{m,k} for k = 0 .. n-1: the steps keep the v they compute, and
     // the last one, which no recomputed step forms, comes from the blur kernel
     auto recompute = [&](int m) -> hipError_t {
+        trace_mark("eed4 recompute of cycle %d queued", m);
         std::vector<const float *> &U = Ur[m & 1];
         float *V = Vset[m & 1];
         U[0] = ckpt + (size_t)m * N;
@@ -1162,6 +1165,7 @@ extern "C" int eed4_backward(const float *ckpt, const uint8_t *mask, const float
     EED4_TRY2(hipStreamWaitEvent(s1, start, 0), "stream wait");
     EED4_TRY2(recompute(M - 1), "recompute step");
     for (int m = M - 1; m >= 0 && rc2 == EED4_OK; --m) {
+        trace_mark("eed4 reverse sweep of cycle %d queued", m);
         EED4_TRY2(hipStreamWaitEvent(s, rec[m & 1], 0), "stream wait");
         if (m >= 1) {
             // set (m-1) & 1 was last read by the reverse sweep of cycle m+1

@@ -352,6 +352,7 @@ int default_step_shape(int R, int B, int H, int W)
 int tune_single_step(const eed4_params *p, int B, int H, int W, float *S, float *X,
                      const uint8_t *mask, hipStream_t s, int *shape)
 {
+    TraceRange range("eed4 step-shape tuning %dx%dx%d", B, H, W);
     const int R = eed4_radius(p->sigma);
     const StepArgs a = make_args(p->sigma, R, p->tau, p->lambda, 0);
     int order[kNumShapes];
@@ -451,6 +452,7 @@ static int run_to_tolerance(const CycleJob &j, float *T, const eed4_params *p,
         if (e != hipSuccess) rc = hip_fail(e, "event");
     }
     auto issue = [&](int m) -> int {
+        trace_mark("eed4 cycle %d queued", m);
         const CycleJob &c = job[m & 1];
         if (ckpt) {
             e = hipMemcpyAsync(ckpt + (size_t)m * N, c.S, sizeof(float) * N,
@@ -476,7 +478,10 @@ static int run_to_tolerance(const CycleJob &j, float *T, const eed4_params *p,
     if (rc == EED4_OK) rc = issue(0);
     for (; rc == EED4_OK; ++m) {
         if (m + 1 < M && (rc = issue(m + 1)) != EED4_OK) break;
-        e = hipEventSynchronize(ev[m & 1]);
+        {
+            TraceRange wait("eed4 wait for the residual of cycle %d", m);
+            e = hipEventSynchronize(ev[m & 1]);
+        }
         if (e != hipSuccess) { rc = hip_fail(e, "residual read-back"); break; }
         evaluate_residuals(host + 2 * (size_t)B * (m & 1), B, *out);
         const double crit = (p->flags & EED4_ABS_TOL) ? out->worst_abs : out->worst_rel;
@@ -517,11 +522,13 @@ static int run_fixed(const CycleJob &j, int M, const eed4_params *p, float *ckpt
     if (rc == EED4_OK && exec && !ckpt && !hist_dev && M >= kGraphCycles) {
         rc = cycle_graph(j, kGraphCycles, &multi, &own_multi);
         for (; rc == EED4_OK && m + kGraphCycles <= M; m += kGraphCycles) {
+            trace_mark("eed4 cycles %d-%d queued", m, m + kGraphCycles - 1);
             e = hipGraphLaunch(multi, s);
             if (e != hipSuccess) rc = hip_fail(e, "graph launch");
         }
     }
     for (; rc == EED4_OK && m < M; ++m) {
+        trace_mark("eed4 cycle %d queued", m);
         if (ckpt) {
             e = hipMemcpyAsync(ckpt + (size_t)m * N, j.S, sizeof(float) * N,
                                hipMemcpyDeviceToDevice, s);
@@ -617,6 +624,8 @@ int eed4_inpaint(float *u, const uint8_t *mask, const float *known, int B, int H
                  const eed4_params *p, float *ckpt, void *ws, size_t ws_bytes, void *stream,
                  eed4_stats *stats, double *hist)
 {
+    TraceRange range("eed4_inpaint %dx%dx%d, up to %d cycles of %d", B, H, W, p ? p->max_cycles : 0,
+                     p ? p->cycle_len : 0);
     int rc = check_params(p, B, H, W);
     if (rc != EED4_OK) return rc;
     if (!u || !mask || !known) return EED4_EINVAL;
@@ -668,6 +677,7 @@ int eed4_inpaint(float *u, const uint8_t *mask, const float *known, int B, int H
 int eed4_fsi_cycle(float *u, const uint8_t *mask, const float *known, int B, int H, int W,
                    const eed4_params *p, void *ws, size_t ws_bytes, void *stream, double *d_sums)
 {
+    TraceRange range("eed4_fsi_cycle %dx%dx%d", B, H, W);
     int rc = check_params(p, B, H, W);
     if (rc != EED4_OK) return rc;
     if (!u || !mask || !known || !d_sums) return EED4_EINVAL;

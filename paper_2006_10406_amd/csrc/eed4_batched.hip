@@ -516,6 +516,7 @@ extern "C" size_t eed4_batched_workspace_size(const eed4_image *imgs, int B, con
 extern "C" int eed4_autotune_batched(const eed4_image *imgs, int B, const eed4_params *p,
                                      void *ws, size_t ws_bytes, void *stream)
 {
+    TraceRange range("eed4_autotune_batched %d images", B);
     int rc = check_images(imgs, B, p);
     if (rc != EED4_OK) return rc;
     BatchLayout L = batch_layout(imgs, B, p);
@@ -532,6 +533,8 @@ extern "C" int eed4_autotune_batched(const eed4_image *imgs, int B, const eed4_p
 extern "C" int eed4_inpaint_batched(const eed4_image *imgs, int B, const eed4_params *p, void *ws,
                                     size_t ws_bytes, void *stream, eed4_stats *stats)
 {
+    TraceRange range("eed4_inpaint_batched %d images, up to %d cycles of %d", B,
+                     p ? p->max_cycles : 0, p ? p->cycle_len : 0);
     int rc = check_images(imgs, B, p);
     if (rc != EED4_OK) return rc;
     BatchLayout L = batch_layout(imgs, B, p);

@@ -4,11 +4,40 @@
 #include "eed4.h"
 #include "eed4_internal.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <cmath>
+#include <cstdio>
 #include <functional>
 #include <string>
 
 namespace eed4 {
+
+// Host-side roctx ranges and marks around the library's calls, cycles and
+// waits (`rocprofv3 --marker-trace` shows them beside the kernel trace).  A
+// range lasts for the lifetime of the object.  Without a tool attached each
+// costs a formatted string and a call that returns at once.
+class TraceRange {
+public:
+    template <typename... A>
+    explicit TraceRange(const char *fmt, A... a)
+    {
+        char buf[160];
+        std::snprintf(buf, sizeof(buf), fmt, a...);
+        roctxRangePushA(buf);
+    }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
+
+template <typename... A>
+inline void trace_mark(const char *fmt, A... a)
+{
+    char buf[160];
+    std::snprintf(buf, sizeof(buf), fmt, a...);
+    roctxMarkA(buf);
+}
 
 // One FSI cycle over a batch of B equal-size images.
 struct CycleJob {

@@ -76,7 +76,8 @@ def test_abi_checks_under_asan_and_ubsan(tmp_path):
         objs = list(ex.map(compile_one, ("eed4_api", "eed4_adjoint")))
     lib = str(tmp_path / "libeed4_san.so")
     subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + SANITIZE
-                   + ["-o", lib] + objs + others, check=True, capture_output=True)
+                   + ["-o", lib] + objs + others + ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"],
+                   check=True, capture_output=True)
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
                         "-m", "not gpu", os.path.join(ROOT, "tests", "test_abi.py")],
                        env=_env(lib), capture_output=True, text=True, timeout=600, cwd=ROOT)
