@@ -112,6 +112,17 @@ def fp64_error(got, ref):
             "rmse": float(np.sqrt(np.mean(d * d))) if d.size else 0.0}
 
 
+def quality(got, truth):
+    """Reconstruction against the synthetic ground truth: MSE and AAE (mean absolute error),
+    the error measures of the paper's experiments (Sec. 4), for grey values in [0, 1] and
+    scaled to the 0..255 grey range the paper's tables use."""
+    import numpy as np
+    d = np.asarray(got, np.float64) - np.asarray(truth, np.float64)
+    mse, aae = float(np.mean(d * d)), float(np.mean(np.abs(d)))
+    return {"mse": mse, "aae": aae, "mse_255": mse * 255.0 ** 2, "aae_255": aae * 255.0,
+            "against": "the synthetic ground-truth image"}
+
+
 def grad_error(got, ref):
     """A gradient against the oracle adjoint: relative L2 and the largest elementwise error
     relative to the largest oracle value."""
@@ -417,11 +428,12 @@ def workload_throughput(eed4, torch, names=("rgb512", "scratch512_thin", "scratc
         ms = e0.elapsed_time(e1)
         px = u0.numel()
         B = px // (wl.H * wl.W)
+        got = u.cpu().numpy()
         res[name] = {"mpix_updates_s": round(px * wl.n * st.cycles / (ms * 1e-3) / 1e6, 1),
                      "ms": round(ms, 3), "cycles": st.cycles, "planes": B,
-                     "shape": eed4.SHAPE_NAMES[eed4.eed4_step_shape(B, wl.H, wl.W, p)]}
+                     "shape": eed4.SHAPE_NAMES[eed4.eed4_step_shape(B, wl.H, wl.W, p)],
+                     "quality": quality(got, pr["image"])}
         # the colour planes are independent: channel 0 stands for the three
-        got = u.cpu().numpy()
         got, q = (got[0], {k: pr[k][0] for k in ("u_init", "mask", "known")}) if B > 1 \
             else (got, pr)
         checks.append((name, deferred_run(got, q, wl, st.cycles,
@@ -450,7 +462,8 @@ def workload_throughput(eed4, torch, names=("rgb512", "scratch512_thin", "scratc
                                "ms": round(ms, 2),
                                "mpix_updates_s": round(wl.H * wl.W * wl.n * st.cycles
                                                        / (ms * 1e-3) / 1e6, 1),
-                               "tol": wl.tol, "cycle_len": wl.n}
+                               "tol": wl.tol, "cycle_len": wl.n,
+                               "quality": quality(u.cpu().numpy(), pr["image"])}
     checks.append(("single512_to_tol", deferred_run(u.cpu().numpy(), pr, wl, st.cycles,
                                                     "the image")))
     return res, checks
