@@ -767,12 +767,16 @@ static int adj_strip_items_t(int H, int W)
     return ((W + G::SW - 1) / G::SW) * ((H + G::OH - 1) / G::OH);
 }
 
+// Segment heights of the strip reverse step per forward strip shape.  The
+// 64-row shapes map to segments of >= 80 rows: at 4096^2 and R = 6 those
+// launch 4,042 waves, which all fit at once at 4 waves per SIMD (>= 64 rows
+// launch 4,730, and the last 16 % ran as a second, nearly empty round).
 template <int R>
 static int adj_items_r(int shape, int H, int W)
 {
     switch (shape) {
     case kShapeStrip:
-    case kShapeStripWide: return adj_strip_items_t<R, 64>(H, W);
+    case kShapeStripWide: return adj_strip_items_t<R, 80>(H, W);
     case kShapeStripTall: return adj_strip_items_t<R, 136>(H, W);
     case kShapeStripShort:
     case kShapeStripWideShort: return adj_strip_items_t<R, 28>(H, W);
@@ -896,7 +900,7 @@ static hipError_t launch_rev_r(const RevStep &t, const StepArgs &a, float il3, f
                                            : hipErrorInvalidValue;
     switch (t.shape) {
     case kShapeStrip:
-    case kShapeStripWide: return launch_rev_strip<R, 64>(t, a, il3, ls, s);
+    case kShapeStripWide: return launch_rev_strip<R, 80>(t, a, il3, ls, s);
     case kShapeStripTall: return launch_rev_strip<R, 136>(t, a, il3, ls, s);
     case kShapeStripShort:
     case kShapeStripWideShort: return launch_rev_strip<R, 28>(t, a, il3, ls, s);
