@@ -515,13 +515,15 @@ __device__ __forceinline__ void adjoint_strip_step(float *lds, const AdjStripArg
         // their segment yield issue slots to those behind, as in the forward
         // strip; when the launch needs more than one round of waves the host
         // leaves this off (late waves would then hold the top priority).  Only
-        // the short segments, which small problems use, carry the code.
+        // the short segments, which small problems use, carry the code.  The
+        // levels stay above 0, the level of the recompute steps that run beside
+        // this kernel on the other stream, so these waves, the critical path,
+        // issue first.
         if (ROWS <= 28 && s.prio) {
             const int left = G::M - it;
-            if (left >= 4) __builtin_amdgcn_s_setprio(3);
-            else if (left == 3) __builtin_amdgcn_s_setprio(2);
-            else if (left == 2) __builtin_amdgcn_s_setprio(1);
-            else __builtin_amdgcn_s_setprio(0);
+            if (left >= 3) __builtin_amdgcn_s_setprio(3);
+            else if (left == 2) __builtin_amdgcn_s_setprio(2);
+            else __builtin_amdgcn_s_setprio(1);
         }
 #pragma unroll
         for (int ph = 0; ph < U; ++ph) {

@@ -314,7 +314,9 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
         // the launch ends with few waves per SIMD to hide latency (about 4.4 of
         // 8 resident on average at 4096^2); this schedule took the 64-row
         // strips from 49 to 44.5 us there, with bitwise the same results.
-        {
+        // The adjoint's recompute steps (VST) stay at the lowest priority: they
+        // run beside the reverse steps, which are the critical path.
+        if constexpr (!VST) {
             const int left = G::M - it;
             if (left >= 4) __builtin_amdgcn_s_setprio(3);
             else if (left == 3) __builtin_amdgcn_s_setprio(2);
