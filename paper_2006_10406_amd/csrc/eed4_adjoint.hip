@@ -1038,7 +1038,10 @@ static int adjoint_shape(const eed4_params *p, RevStep t, hipStream_t s, int *sh
     // the wide forward shapes map onto the same reverse strips as their heights
     const int cands[] = {kShapeStrip, 0, kShapeStripTall, kShapeStripShort, kShapeStripTiny};
     const size_t N = (size_t)t.B * t.H * t.W;
-    hipError_t e = launch_fill(t.ac, N, 0.0f, s);
+    // the strip candidates read the presmoothed state t.v
+    const StepArgs a0 = make_args(p->sigma, t.R, p->tau, p->lambda, 0, model_of_flags(p->flags));
+    hipError_t e = launch_blur(t.R, t.u, const_cast<float *>(t.v), t.B, t.H, t.W, a0, s);
+    if (e == hipSuccess) e = launch_fill(t.ac, N, 0.0f, s);
     if (e != hipSuccess) return hip_fail(e, "adjoint autotune");
     int best = cands[0];
     const int rc = tune_pick(
@@ -1107,8 +1110,6 @@ extern "C" int eed4_backward(const float *ckpt, const uint8_t *mask, const float
         probe.u = ckpt + (size_t)(M - 1) * N;
         probe.an = grad_u;
         probe.v = Vbuf;
-        const StepArgs a0 = make_args(p->sigma, R, p->tau, p->lambda, 0, model_of_flags(p->flags));
-        EED4_TRY(launch_blur(R, probe.u, Vbuf, B, H, W, a0, s), "presmoothing");
         if ((rc = adjoint_shape(p, probe, s, &t.shape)) != EED4_OK) return rc;
     }
     const bool keep_v = is_strip(t.shape);      // the strip reverse step reads K_sigma * u^k
