@@ -331,7 +331,7 @@ __global__ __launch_bounds__(256) void adjoint_b_kernel(const float *qx_all, con
                                                         float *ac_all, float *ap_all,
                                                         const uint8_t *__restrict__ mask_all,
                                                         int H, int W, int nbx,
-                                                        int tiles_per_img, StepArgs a, int first)
+                                                        int tiles_per_img, StepArgs a, int kflags)
 {
     using G = AdjBGeo<R>;
     constexpr int TW = G::TW, TH = G::TH;
@@ -379,9 +379,10 @@ __global__ __launch_bounds__(256) void adjoint_b_kernel(const float *qx_all, con
         const bool m = mask_all[gi] != 0;
         const float rv = m ? 0.0f : anv;
         const float z = pr_all[gi] + cq;
-        float acv = fmaf(a.alpha, fmaf(-a.tau, z, rv), ac_all[gi]);
+        const float acold = (kflags & 2) ? 0.0f : ac_all[gi];  // a cycle's first reverse step
+        float acv = fmaf(a.alpha, fmaf(-a.tau, z, rv), acold);
         const float back = (1.0f - a.alpha) * rv;
-        if (first) acv += back;
+        if (kflags & 1) acv += back;
         else ap_all[gi] = back;
         if (m) acv += anv;              // known pixel: running sum of ubar
         ac_all[gi] = acv;
@@ -424,6 +425,7 @@ struct AdjStripArgs {
     int H, W, X0, Y0;
     float tau, alpha, il2, il3; // il2 = 1/lambda^2, il3 = 1/lambda^3
     int first;                  // k == 0: the (1-alpha) r term goes to ubar^k itself
+    int fresh;                  // k == n-1: ubar^k starts at 0 (not read)
     int model;                  // tensor variant (GEN kernels only)
     int prio;                   // lower the issue priority along the segment
 };
@@ -457,6 +459,9 @@ __device__ __forceinline__ void adjoint_strip_step(float *lds, const AdjStripArg
     const __amdgpu_buffer_rsrc_t rs_u = buffer_rsrc(s.u + base, (unsigned)nb * W4);
     const __amdgpu_buffer_rsrc_t rs_an = buffer_rsrc(s.an + base, (unsigned)nb * W4);
     const __amdgpu_buffer_rsrc_t rs_ac = buffer_rsrc(s.ac + base, (unsigned)nb * W4);
+    // ubar^k as read: no records in a cycle's first reverse step, where it
+    // starts at 0 (its loads then read 0, and no clearing pass is needed)
+    const __amdgpu_buffer_rsrc_t rs_acl = buffer_rsrc(s.ac + base, s.fresh ? 0u : (unsigned)nb * W4);
     // at k = 0 the (1 - alpha) r term stays in ubar^k: the ubar^{k-1} resource
     // then has no records, so its stores are dropped
     const __amdgpu_buffer_rsrc_t rs_ap = buffer_rsrc(s.ap + base, s.first ? 0u : (unsigned)nb * W4);
@@ -500,7 +505,7 @@ __device__ __forceinline__ void adjoint_strip_step(float *lds, const AdjStripArg
         oc = oc > H - 1 ? H - 1 : oc;
         const unsigned ro = (unsigned)(oc - b0);
         r.oa = buf_f32(rs_an, vo4, ro * W4);
-        r.oc = buf_f32(rs_ac, vo4, ro * W4);
+        r.oc = buf_f32(rs_acl, vo4, ro * W4);
         r.omk = __builtin_amdgcn_raw_buffer_load_b8(rs_m, vo1, ro * (unsigned)W, 0);
         ty.next(H);
         ++on;
@@ -614,7 +619,7 @@ __device__ __forceinline__ void adjoint_strip_body(const float *v_all, const flo
                                                    const uint8_t *__restrict__ mask_all, int H,
                                                    int W, int nstrip, int per_img, int nitems,
                                                    const StepArgs &a, float il3, float lam_scale,
-                                                   int first, int prio, float *lam_partials,
+                                                   int kflags, int prio, float *lam_partials,
                                                    int lam_stride)
 {
     using G = AdjStripGeo<R, ROWS>;
@@ -641,7 +646,8 @@ __device__ __forceinline__ void adjoint_strip_body(const float *v_all, const flo
     s.alpha = a.alpha;
     s.il2 = a.inv_lam2;
     s.il3 = il3;
-    s.first = first;
+    s.first = kflags & 1;
+    s.fresh = (kflags >> 1) & 1;
     s.model = a.model;
     s.prio = prio;
     adjoint_strip_step<R, ROWS, GEN>(lds + wave * G::LDS, s, a.w,
@@ -655,12 +661,12 @@ __global__ __launch_bounds__(256) void adjoint_strip_kernel(const float *v_all, 
                                                             const uint8_t *__restrict__ mask_all,
                                                             int H, int W, int nstrip, int per_img,
                                                             int nitems, StepArgs a, float il3,
-                                                            float lam_scale, int first,
+                                                            float lam_scale, int kflags,
                                                             int prio, float *lam_partials,
                                                             int lam_stride)
 {
     adjoint_strip_body<R, ROWS, false>(v_all, u_all, an_all, ac_all, ap_all, mask_all, H, W, nstrip,
-                                       per_img, nitems, a, il3, lam_scale, first, prio,
+                                       per_img, nitems, a, il3, lam_scale, kflags, prio,
                                        lam_partials, lam_stride);
 }
 
@@ -670,11 +676,11 @@ template <int R>
 __global__ __launch_bounds__(256) void adjoint_strip_model_kernel(
     const float *v_all, const float *u_all, const float *an_all, float *ac_all, float *ap_all,
     const uint8_t *__restrict__ mask_all, int H, int W, int nstrip, int per_img, int nitems,
-    StepArgs a, float il3, float lam_scale, int first, int prio, float *lam_partials,
+    StepArgs a, float il3, float lam_scale, int kflags, int prio, float *lam_partials,
     int lam_stride)
 {
     adjoint_strip_body<R, 28, true>(v_all, u_all, an_all, ac_all, ap_all, mask_all, H, W, nstrip,
-                                    per_img, nitems, a, il3, lam_scale, first, prio, lam_partials,
+                                    per_img, nitems, a, il3, lam_scale, kflags, prio, lam_partials,
                                     lam_stride);
 }
 
@@ -710,13 +716,36 @@ __global__ __launch_bounds__(1024) void pairwise_pass_kernel(const float *in, lo
 // binary counter): slot i holds the sum of a block of 2^i cycles.  Adding the
 // j-th cycle sum merges it with the t = (trailing ones of j) lowest slots and
 // stores the block in slot t.
+__device__ __forceinline__ void lambda_carry(float v, float *slots, int B, int b, int t)
+{
+    for (int i = 0; i < t; ++i) v = slots[(size_t)i * B + b] + v;
+    slots[(size_t)t * B + b] = v;
+}
+
 __global__ void lambda_carry_kernel(const float *cyc, float *slots, int B, int t)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= B) return;
-    float v = cyc[b];
-    for (int i = 0; i < t; ++i) v = slots[(size_t)i * B + b] + v;
-    slots[(size_t)t * B + b] = v;
+    lambda_carry(cyc[b], slots, B, b, t);
+}
+
+// Both of the above in one launch when a cycle's partials fit one pairwise
+// pass (L <= 2048 per image): the same tree and the same cascade, so the same
+// bits, with one launch per cycle instead of two.
+__global__ __launch_bounds__(1024) void lambda_cycle_kernel(const float *in, long long L,
+                                                            float *slots, int B, int t)
+{
+    __shared__ float sv[2048];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const float *p = in + (size_t)b * L;
+    sv[tid] = tid < L ? p[tid] : 0.0f;
+    sv[tid + 1024] = tid + 1024 < L ? p[tid + 1024] : 0.0f;
+    __syncthreads();
+    for (int s = 1024; s > 0; s >>= 1) {
+        if (tid < s) sv[tid] = sv[tid] + sv[tid + s];
+        __syncthreads();
+    }
+    if (tid == 0) lambda_carry(sv[0], slots, B, b, t);
 }
 
 // dL/dlambda = the occupied slots (the set bits of the cycle count M), largest
@@ -822,6 +851,8 @@ struct RevStep {
     float *lp;               // lambda partials of this step: image b, item r at lp[b * ls + r]
     int ls;                  // ... image stride (cycle_len * items per image)
     int B, H, W, R, shape, first;
+    int fresh;               // a cycle's first reverse step: ubar^k starts at 0 (not read)
+    int kflags() const { return (first ? 1 : 0) | (fresh ? 2 : 0); }
 };
 
 template <int R>
@@ -836,7 +867,7 @@ static hipError_t launch_rev_tile(const RevStep &t, const StepArgs &a, float il3
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((adjoint_b_kernel<R>), dim3((unsigned)(tpi * t.B)), dim3(256), 0, s, t.qx,
-                       t.qy, t.pr, t.an, t.ac, t.ap, t.mask, t.H, t.W, nbx, tpi, a, t.first);
+                       t.qy, t.pr, t.an, t.ac, t.ap, t.mask, t.H, t.W, nbx, tpi, a, t.kflags());
     return hipGetLastError();
 }
 
@@ -870,7 +901,7 @@ static hipError_t launch_rev_strip(const RevStep &t, const StepArgs &a, float il
     const int prio = nitems <= cap ? 1 : 0;
     hipLaunchKernelGGL((adjoint_strip_kernel<R, ROWS>), dim3(nblk), dim3(256), 0, s, t.v, t.u, t.an,
                        t.ac, t.ap, t.mask, t.H, t.W, nstrip, per_img, (int)nitems, a, il3, ls,
-                       t.first, prio, t.lp, t.ls);
+                       t.kflags(), prio, t.lp, t.ls);
     return hipGetLastError();
 }
 
@@ -888,7 +919,7 @@ static hipError_t launch_rev_model(const RevStep &t, const StepArgs &a, float il
     const int prio = nitems <= cap ? 1 : 0;
     hipLaunchKernelGGL((adjoint_strip_model_kernel<R>), dim3(nblk), dim3(256), 0, s, t.v, t.u, t.an,
                        t.ac, t.ap, t.mask, t.H, t.W, nstrip, per_img, (int)nitems, a, il3, ls,
-                       t.first, prio, t.lp, t.ls);
+                       t.kflags(), prio, t.lp, t.ls);
     return hipGetLastError();
 }
 
@@ -1049,6 +1080,7 @@ static int adjoint_shape(const eed4_params *p, RevStep t, hipStream_t s, int *sh
         [&](int c) {
             t.shape = c;
             t.first = 0;
+            t.fresh = 0;                       // ac was cleared above
             return (int)EED4_OK;
         },
         [&](int) { return launch_reverse_step(t, p, p->cycle_len - 1, s); }, "adjoint autotune",
@@ -1179,7 +1211,6 @@ extern "C" int eed4_backward(const float *ckpt, const uint8_t *mask, const float
             if (m + 1 <= M - 1) EED4_TRY2(hipStreamWaitEvent(s1, done[(m + 1) & 1], 0), "stream wait");
             EED4_TRY2(recompute(m - 1), "recompute step");
         }
-        EED4_TRY2(launch_fill(ac, N, 0.0f, s), "fill");
         const std::vector<const float *> &U = Ur[m & 1];
         for (int k = n - 1; k >= 0 && rc2 == EED4_OK; --k) {
             t.u = U[k];
@@ -1188,6 +1219,7 @@ extern "C" int eed4_backward(const float *ckpt, const uint8_t *mask, const float
             t.ac = ac;
             t.ap = ap;
             t.first = k == 0 ? 1 : 0;
+            t.fresh = k == n - 1 ? 1 : 0;          // ubar^{n-1} starts at 0
             t.lp = lp + (size_t)k * items;
             EED4_TRY2(launch_reverse_step(t, p, k, s), "reverse step");
             // ubar^k is complete in ac; ap holds the start of ubar^{k-1}
@@ -1201,9 +1233,16 @@ extern "C" int eed4_backward(const float *ckpt, const uint8_t *mask, const float
         const int j = M - 1 - m;                              // cycles summed before this one
         int carries = 0;
         while ((j >> carries) & 1) ++carries;
-        EED4_TRY2(launch_pairwise_sum(lp, (long long)n * items, B, (float *)(base + L.t1),
-                                      (float *)(base + L.t2), cyc, s), "lambda sum");
-        EED4_TRY2(launch_lambda_carry(cyc, slots, B, carries, s), "lambda cascade");
+        const long long np = (long long)n * items;
+        if (np <= 2048) {
+            hipLaunchKernelGGL(lambda_cycle_kernel, dim3(B), dim3(1024), 0, s, lp, np, slots, B,
+                               carries);
+            EED4_TRY2(hipGetLastError(), "lambda sum");
+        } else {
+            EED4_TRY2(launch_pairwise_sum(lp, np, B, (float *)(base + L.t1),
+                                          (float *)(base + L.t2), cyc, s), "lambda sum");
+            EED4_TRY2(launch_lambda_carry(cyc, slots, B, carries, s), "lambda cascade");
+        }
     }
 #undef EED4_TRY2
     for (auto &x : ev) (void)hipEventDestroy(x);
