@@ -474,10 +474,18 @@ static int run_to_tolerance(const CycleJob &j, float *T, const eed4_params *p,
         e = hipEventRecord(ev[m & 1], s);
         return e == hipSuccess ? (int)EED4_OK : hip_fail(e, "residual read-back");
     };
+    // The residual decays about geometrically from cycle to cycle: when the last
+    // two criteria predict that cycle m comes within 5 % of tol or below it,
+    // m+1 is not queued before m's residual is read.  That saves the wasted
+    // cycle at the stop; a wrong guess costs one host round trip of GPU idle
+    // time, far less than a cycle, hence the generous margin.
+    const double tol = (double)p->tol;
+    double c1 = -1.0, c2 = -1.0;                     // criteria of cycles m-1, m-2
     int m = 0;
     if (rc == EED4_OK) rc = issue(0);
     for (; rc == EED4_OK; ++m) {
-        if (m + 1 < M && (rc = issue(m + 1)) != EED4_OK) break;
+        const bool stop_likely = c1 > 0.0 && c2 > c1 && c1 * (c1 / c2) < 1.05 * tol;
+        if (!stop_likely && m + 1 < M && (rc = issue(m + 1)) != EED4_OK) break;
         {
             TraceRange wait("eed4 wait for the residual of cycle %d", m);
             e = hipEventSynchronize(ev[m & 1]);
@@ -485,7 +493,10 @@ static int run_to_tolerance(const CycleJob &j, float *T, const eed4_params *p,
         if (e != hipSuccess) { rc = hip_fail(e, "residual read-back"); break; }
         evaluate_residuals(host + 2 * (size_t)B * (m & 1), B, *out);
         const double crit = (p->flags & EED4_ABS_TOL) ? out->worst_abs : out->worst_rel;
-        if (out->diverged || crit < (double)p->tol || m == M - 1) break;
+        if (out->diverged || crit < tol || m == M - 1) break;
+        if (stop_likely && (rc = issue(m + 1)) != EED4_OK) break;
+        c2 = c1;
+        c1 = crit;
     }
     out->cycles = m + 1;
     // wait for the cycle queued beyond the stop point, then bring the result home
