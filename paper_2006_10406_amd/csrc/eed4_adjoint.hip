@@ -487,6 +487,10 @@ __device__ __forceinline__ void adjoint_strip_step(float *lds, const AdjStripArg
     float v_m1 = 0.0f, v_m2 = 0.0f;                          // v at rows g, g-1
     float u_m1 = 0.0f, u_m2 = 0.0f;                          // u at rows g, g-1
     float r_m1 = 0.0f, r_m2 = 0.0f;                          // r at rows g, g-1
+    // lane-neighbour sums (row g) and differences (rows g, g-1) of u and r: each
+    // row's two lane shifts are taken once, when it arrives
+    float su_m1 = 0.0f, du_m1 = 0.0f, du_m2 = 0.0f;
+    float sr_m1 = 0.0f, dr_m1 = 0.0f, dr_m2 = 0.0f;
     float txx_p = 0.0f, tyy_p = 0.0f, tyy_pp = 0.0f;         // D:A at rows g-1 (g-2 for yy)
     float z_p = 0.0f, z_pp = 0.0f;                           // (D:A)xy(l+1)-(D:A)xy(l-1)
     float qx_p = 0.0f, qy_p = 0.0f, qy_pp = 0.0f;            // q at rows g-1 (g-2 for y)
@@ -542,20 +546,28 @@ __device__ __forceinline__ void adjoint_strip_step(float *lds, const AdjStripArg
             const float r_p1 = cur.rmk ? 0.0f : cur.rn;
             const float gxs = from_next_lane(v_m1) - from_prev_lane(v_m1);  // 2 gx
             const float gys = v_p1 - v_m2;                                   // 2 gy
-            const float hxx = fmaf(-2.0f, u_m1, from_prev_lane(u_m1) + from_next_lane(u_m1));
+            const float pu = from_prev_lane(u_p1), nu = from_next_lane(u_p1);
+            const float pr_ = from_prev_lane(r_p1), nr = from_next_lane(r_p1);
+            const float su_p1 = pu + nu, du_p1 = nu - pu;                    // row g+1
+            const float sr_p1 = pr_ + nr, dr_p1 = nr - pr_;
+            const float hxx = fmaf(-2.0f, u_m1, su_m1);
             const float hyy = fmaf(-2.0f, u_m1, u_m2 + u_p1);
-            const float hxy = 0.25f * ((from_next_lane(u_p1) + from_prev_lane(u_m2)) -
-                                       (from_prev_lane(u_p1) + from_next_lane(u_m2)));
-            const float axx = fmaf(-2.0f, r_m1, from_prev_lane(r_m1) + from_next_lane(r_m1));
+            const float hxy = 0.25f * (du_p1 - du_m2);
+            const float axx = fmaf(-2.0f, r_m1, sr_m1);
             const float ayy = fmaf(-2.0f, r_m1, r_m2 + r_p1);
-            const float axy = 0.25f * ((from_next_lane(r_p1) - from_prev_lane(r_p1)) -
-                                       (from_next_lane(r_m2) - from_prev_lane(r_m2)));
+            const float axy = 0.25f * (dr_p1 - dr_m2);
             v_m2 = v_m1;
             v_m1 = v_p1;
             u_m2 = u_m1;
             u_m1 = u_p1;
             r_m2 = r_m1;
             r_m1 = r_p1;
+            su_m1 = su_p1;
+            du_m2 = du_m1;
+            du_m1 = du_p1;
+            sr_m1 = sr_p1;
+            dr_m2 = dr_m1;
+            dr_m1 = dr_p1;
             float tx, ty_, txy, qx, qy, dl;
             adjoint_point<GEN>(0.5f * gxs, 0.5f * gys, s.il2, s.il3, axx, ayy, axy, hxx, hyy, hxy,
                                tx, ty_, txy, qx, qy, dl, s.model);
