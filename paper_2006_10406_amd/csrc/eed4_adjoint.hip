@@ -118,10 +118,8 @@ __device__ __forceinline__ void adjoint_point(float gx, float gy, float inv_lam2
     const float amb = a - b, c2 = c + c;
     const float a1 = fmaf(a, axx, fmaf(b, ayy, c2 * axy));
     const float a3 = fmaf(c, ayy - axx, amb * axy);
-    const float at = fmaf(b, axx, fmaf(a, ayy, -c2 * axy));
     const float h1 = fmaf(a, hxx, fmaf(b, hyy, c2 * hxy));
     const float h3 = fmaf(c, hyy - hxx, amb * hxy);
-    const float ht = fmaf(b, hxx, fmaf(a, hyy, -c2 * hxy));
     // D : A
     const float k1 = (mu1 - 1.0f) * a1;
     const float k3 = (mu3 - 1.0f) * a3;
@@ -136,20 +134,25 @@ __device__ __forceinline__ void adjoint_point(float gx, float gy, float inv_lam2
         const float Y = fmaf(md.G1, a1 * h1, 2.0f * md.G3 * (a3 * h3));
         de_ds = 2.0f * s * inv_lam2 * Y;
         dl = -2.0f * (s2 * inv_lam3) * Y;
+        const float at = fmaf(b, axx, fmaf(a, ayy, -c2 * axy));
+        const float ht = fmaf(b, hxx, fmaf(a, hyy, -c2 * hxy));
         const float p1 = fmaf(a3, h1, a1 * h3);
         const float p2 = fmaf(at - a1, h3, a3 * (ht - h1));
         dth = 2.0f * s * inv_lam2 * fmaf(md.Q1, p1, md.Q3 * p2);
     } else {
         // derivatives: dmu1/ds = -s mu1^3 / lam^2, dmu3/ds = -s mu1^(5/2) / (2 lam^2)
         const float m12 = mu1 * mu1;
-        const float X = fmaf(m12 * mu1, a1 * h1, m12 * mu3 * (a3 * h3));
-        de_ds = -s * inv_lam2 * X;
+        const float X = m12 * fmaf(mu1, a1 * h1, mu3 * (a3 * h3));
+        const float F = s * inv_lam2;
+        de_ds = -F * X;
         dl = (s2 * inv_lam3) * X;
-        // (mu1 - 1)/s = -s mu1^2 / (lam^2 (1 + mu1)), (mu3 - 1)/s = that / (1 + mu3)
+        // (mu1 - 1)/s = -s mu1^2 / (lam^2 (1 + mu1)), (mu3 - 1)/s = that / (1 + mu3).
+        // With a + b = 1 for the unit n, t.A.t - n.A.n = (axx + ayy) - 2 a1 and the same
+        // for H; where G = 0 (n = 0) the factor F = 0 zeroes the whole term.
         const float rp = __builtin_amdgcn_rcpf((1.0f + mu1) * (1.0f + mu3));
         const float p1 = fmaf(a3, h1, a1 * h3);
-        const float p2 = fmaf(at - a1, h3, a3 * (ht - h1));
-        dth = -2.0f * s * m12 * inv_lam2 * rp * fmaf(p1, 1.0f + mu3, p2);
+        const float p2 = fmaf(fmaf(-2.0f, a1, axx + ayy), h3, a3 * fmaf(-2.0f, h1, hxx + hyy));
+        dth = -2.0f * (F * m12 * rp) * fmaf(p1, 1.0f + mu3, p2);
     }
     qx = fmaf(nx, de_ds, -ny * dth);
     qy = fmaf(ny, de_ds, nx * dth);
