@@ -240,6 +240,13 @@ def aligned_workspace(torch, nbytes, dev):
     return buf[(-buf.data_ptr()) % 256:]
 
 
+def seeded_direction(torch, shape, seed, dev):
+    """dL/du^M for the adjoint timings: seeded N(0, 1e-6) values, the same every run."""
+    import numpy as np
+    g = np.random.default_rng(seed + 7919).standard_normal(shape).astype(np.float32) * 1e-3
+    return torch.from_numpy(g).to(dev)
+
+
 def adjoint_ratio(eed4, torch, args):
     """Forward (with per-cycle checkpoints) vs backward time on 16 x 256 x 256."""
     from synth import WORKLOADS, make_batch
@@ -252,7 +259,7 @@ def adjoint_ratio(eed4, torch, args):
     B, H, W = u0.shape
     p = eed4.params(wl.lam, wl.sigma, wl.tau, wl.n, wl.M)
     ck = torch.empty((wl.M, B, H, W), dtype=torch.float32, device=dev)
-    gu = torch.randn((B, H, W), device=dev) * 1e-3
+    gu = seeded_direction(torch, (B, H, W), wl.seed_base, dev)
     gk = torch.empty_like(gu)
     gi = torch.empty_like(gu)
     gl = torch.empty(B, device=dev)
@@ -553,7 +560,7 @@ def adjoint_probe(eed4, torch):
         ck = torch.empty((M, B, H, W), dtype=torch.float32, device="cuda")
         u = u0.clone()
         eed4.eed4_inpaint(u, mask, known, p, ckpt=ck)
-        gu = torch.randn((B, H, W), device="cuda") * 1e-3
+        gu = seeded_direction(torch, (B, H, W), wl.seed_base, "cuda")
         gk, gi = torch.empty_like(gu), torch.empty_like(gu)
         gl = torch.empty(B, device="cuda")
         for rep in range(2):          # the first call also picks the reverse-step kernel

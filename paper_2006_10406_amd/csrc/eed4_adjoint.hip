@@ -42,8 +42,9 @@ namespace eed4 {
 constexpr int kAdjTW = 64, kAdjTH = 16;
 
 // Per-point pieces of the adjoint.  (gx, gy) = G = grad u_sigma; A = Hessian
-// of r, H = Hessian of u.  Outputs: D(G) : A, q = de/dG and de/dlambda with
-// e = A : D(G) : H.  In the gradient frame n = G/|G|, t = n rotated by +90
+// of r, H = Hessian of u.  Outputs: D(G) : A, q = de/dG and s de/ds with
+// e = A : D(G) : H, s = |G|; mu depends on s/lambda only, so de/dlambda =
+// -(s/lambda) de/ds, and the 1/lambda goes into the per-step scale.  In the gradient frame n = G/|G|, t = n rotated by +90
 // degrees, e = A:H + (mu1 - 1) a1 h1 + 2 (mu3 - 1) a3 h3 with a1 = n.A.n,
 // a3 = t.A.n; d/ds and d/dtheta of it give q = (de/ds) n + (1/s)(de/dtheta) t.
 // Eigenvalue data of a tensor variant (diffusivities of Table 7, mu3 choices
@@ -94,11 +95,10 @@ __device__ __forceinline__ MuData model_mu_data(float x, int model)
 }
 
 template <bool GEN = false>
-__device__ __forceinline__ void adjoint_point(float gx, float gy, float inv_lam2, float inv_lam3,
-                                              float axx, float ayy, float axy, float hxx,
-                                              float hyy, float hxy, float &txx, float &tyy,
-                                              float &txy, float &qx, float &qy, float &dl,
-                                              int model = 0)
+__device__ __forceinline__ void adjoint_point(float gx, float gy, float inv_lam2, float axx,
+                                              float ayy, float axy, float hxx, float hyy,
+                                              float hxy, float &txx, float &tyy, float &txy,
+                                              float &qx, float &qy, float &sds, int model = 0)
 {
     const float s2 = fmaf(gx, gx, gy * gy);
     float mu1, mu3;
@@ -121,19 +121,18 @@ __device__ __forceinline__ void adjoint_point(float gx, float gy, float inv_lam2
     const float h1 = fmaf(a, hxx, fmaf(b, hyy, c2 * hxy));
     const float h3 = fmaf(c, hyy - hxx, amb * hxy);
     // D : A
-    const float k1 = (mu1 - 1.0f) * a1;
-    const float k3 = (mu3 - 1.0f) * a3;
+    const float k1 = fmaf(mu1, a1, -a1);         // (mu1 - 1) a1
+    const float k3 = fmaf(mu3, a3, -a3);         // (mu3 - 1) a3
     const float k3c2 = k3 * c2;
     txx = fmaf(k1, a, axx - k3c2);
     tyy = fmaf(k1, b, ayy + k3c2);
     txy = fmaf(k1, c, fmaf(k3, amb, axy));
     float de_ds, dth;
     if constexpr (GEN) {
-        // with x = s^2/lambda^2: d mu/ds = 2 s/lambda^2 dmu/dx, d mu/dlambda =
-        // -2 s^2/lambda^3 dmu/dx, and (mu - 1)/s = s/lambda^2 (mu - 1)/x
+        // with x = s^2/lambda^2: d mu/ds = 2 s/lambda^2 dmu/dx and
+        // (mu - 1)/s = s/lambda^2 (mu - 1)/x
         const float Y = fmaf(md.G1, a1 * h1, 2.0f * md.G3 * (a3 * h3));
         de_ds = 2.0f * s * inv_lam2 * Y;
-        dl = -2.0f * (s2 * inv_lam3) * Y;
         const float at = fmaf(b, axx, fmaf(a, ayy, -c2 * axy));
         const float ht = fmaf(b, hxx, fmaf(a, hyy, -c2 * hxy));
         const float p1 = fmaf(a3, h1, a1 * h3);
@@ -141,21 +140,19 @@ __device__ __forceinline__ void adjoint_point(float gx, float gy, float inv_lam2
         dth = 2.0f * s * inv_lam2 * fmaf(md.Q1, p1, md.Q3 * p2);
     } else {
         // derivatives: dmu1/ds = -s mu1^3 / lam^2, dmu3/ds = -s mu1^(5/2) / (2 lam^2)
-        const float m12 = mu1 * mu1;
-        const float X = m12 * fmaf(mu1, a1 * h1, mu3 * (a3 * h3));
-        const float F = s * inv_lam2;
-        de_ds = -F * X;
-        dl = (s2 * inv_lam3) * X;
+        const float Fm = (s * inv_lam2) * (mu1 * mu1);            // s mu1^2 / lam^2
+        de_ds = -Fm * fmaf(mu1, a1 * h1, mu3 * (a3 * h3));
         // (mu1 - 1)/s = -s mu1^2 / (lam^2 (1 + mu1)), (mu3 - 1)/s = that / (1 + mu3).
         // With a + b = 1 for the unit n, t.A.t - n.A.n = (axx + ayy) - 2 a1 and the same
-        // for H; where G = 0 (n = 0) the factor F = 0 zeroes the whole term.
-        const float rp = __builtin_amdgcn_rcpf((1.0f + mu1) * (1.0f + mu3));
+        // for H; where G = 0 (n = 0) the factor Fm = 0 zeroes the whole term.
+        const float rp = __builtin_amdgcn_rcpf(fmaf(-0.5f, mu1, -0.5f) * (1.0f + mu3));  // -2/(..)
         const float p1 = fmaf(a3, h1, a1 * h3);
         const float p2 = fmaf(fmaf(-2.0f, a1, axx + ayy), h3, a3 * fmaf(-2.0f, h1, hxx + hyy));
-        dth = -2.0f * (F * m12 * rp) * fmaf(p1, 1.0f + mu3, p2);
+        dth = (Fm * rp) * fmaf(p1, 1.0f + mu3, p2);
     }
     qx = fmaf(nx, de_ds, -ny * dth);
     qy = fmaf(ny, de_ds, nx * dth);
+    sds = s * de_ds;
 }
 
 // The workgroup's sum of v, on thread 0: a pairwise tree over the lanes of
@@ -189,7 +186,7 @@ template <int R>
 __global__ __launch_bounds__(256) void adjoint_a_kernel(const float *u_all, const float *an_all,
                                                         const uint8_t *__restrict__ mask_all,
                                                         int H, int W, int nbx, int tiles_per_img,
-                                                        StepArgs a, float il3, float lam_scale,
+                                                        StepArgs a, float lam_scale,
                                                         float *qx_all, float *qy_all,
                                                         float *pr_all, float *lam_partials,
                                                         int lam_stride)
@@ -262,15 +259,15 @@ __global__ __launch_bounds__(256) void adjoint_a_kernel(const float *u_all, cons
             float axx = (rr[-1] - rc) + (rr[1] - rc);
             float ayy = (rr[-G::RW] - rc) + (rr[G::RW] - rc);
             float axy = 0.25f * ((rr[G::RW + 1] + rr[-G::RW - 1]) - (rr[G::RW - 1] + rr[-G::RW + 1]));
-            float qx, qy, dl;
-            adjoint_point(gx, gy, a.inv_lam2, il3, axx, ayy, axy, hxx, hyy, hxy, txx[k], tyy[k],
-                          txy[k], qx, qy, dl);
+            float qx, qy, sds;
+            adjoint_point(gx, gy, a.inv_lam2, axx, ayy, axy, hxx, hyy, hxy, txx[k], tyy[k], txy[k],
+                          qx, qy, sds);
             int yy = gy0 + pr - 1, xx = gx0 + pc - 1;
             if (pr >= 1 && pr <= TH && pc >= 1 && pc <= TW && yy < H && xx < W) {
                 size_t gi = off + (size_t)yy * W + xx;
                 qx_all[gi] = qx;
                 qy_all[gi] = qy;
-                dlsum += dl;
+                dlsum += sds;
             }
         }
     }
@@ -426,7 +423,7 @@ struct AdjStripArgs {
     float *ac, *ap;             // ubar^k (accumulated in place), ubar^{k-1} contribution
     const uint8_t *mask;
     int H, W, X0, Y0;
-    float tau, alpha, il2, il3; // il2 = 1/lambda^2, il3 = 1/lambda^3
+    float tau, alpha, il2;      // il2 = 1/lambda^2
     int first;                  // k == 0: the (1-alpha) r term goes to ubar^k itself
     int fresh;                  // k == n-1: ubar^k starts at 0 (not read)
     int model;                  // tensor variant (GEN kernels only)
@@ -571,11 +568,11 @@ __device__ __forceinline__ void adjoint_strip_step(float *lds, const AdjStripArg
             sr_m1 = sr_p1;
             dr_m2 = dr_m1;
             dr_m1 = dr_p1;
-            float tx, ty_, txy, qx, qy, dl;
-            adjoint_point<GEN>(0.5f * gxs, 0.5f * gys, s.il2, s.il3, axx, ayy, axy, hxx, hyy, hxy,
-                               tx, ty_, txy, qx, qy, dl, s.model);
+            float tx, ty_, txy, qx, qy, sds;
+            adjoint_point<GEN>(0.5f * gxs, 0.5f * gys, s.il2, axx, ayy, axy, hxx, hyy, hxy, tx, ty_,
+                               txy, qx, qy, sds, s.model);
             const int g = ybase + i - 1;                              // image row of S3
-            dsum += (g >= s.Y0 && g < yend && out_lane) ? dl : 0.0f;
+            dsum += (g >= s.Y0 && g < yend && out_lane) ? sds : 0.0f;
             const float z = from_next_lane(txy) - from_prev_lane(txy);
 
             // ---- S4 at row g - 1: P(u) r and d = -div q ----
@@ -633,7 +630,7 @@ __device__ __forceinline__ void adjoint_strip_body(const float *v_all, const flo
                                                    float *ac_all, float *ap_all,
                                                    const uint8_t *__restrict__ mask_all, int H,
                                                    int W, int nstrip, int per_img, int nitems,
-                                                   const StepArgs &a, float il3, float lam_scale,
+                                                   const StepArgs &a, float lam_scale,
                                                    int kflags, int prio, float *lam_partials,
                                                    int lam_stride)
 {
@@ -660,7 +657,6 @@ __device__ __forceinline__ void adjoint_strip_body(const float *v_all, const flo
     s.tau = a.tau;
     s.alpha = a.alpha;
     s.il2 = a.inv_lam2;
-    s.il3 = il3;
     s.first = kflags & 1;
     s.fresh = (kflags >> 1) & 1;
     s.model = a.model;
@@ -675,13 +671,13 @@ __global__ __launch_bounds__(256) void adjoint_strip_kernel(const float *v_all, 
                                                             float *ac_all, float *ap_all,
                                                             const uint8_t *__restrict__ mask_all,
                                                             int H, int W, int nstrip, int per_img,
-                                                            int nitems, StepArgs a, float il3,
+                                                            int nitems, StepArgs a,
                                                             float lam_scale, int kflags,
                                                             int prio, float *lam_partials,
                                                             int lam_stride)
 {
     adjoint_strip_body<R, ROWS, false>(v_all, u_all, an_all, ac_all, ap_all, mask_all, H, W, nstrip,
-                                       per_img, nitems, a, il3, lam_scale, kflags, prio,
+                                       per_img, nitems, a, lam_scale, kflags, prio,
                                        lam_partials, lam_stride);
 }
 
@@ -691,11 +687,11 @@ template <int R>
 __global__ __launch_bounds__(256) void adjoint_strip_model_kernel(
     const float *v_all, const float *u_all, const float *an_all, float *ac_all, float *ap_all,
     const uint8_t *__restrict__ mask_all, int H, int W, int nstrip, int per_img, int nitems,
-    StepArgs a, float il3, float lam_scale, int kflags, int prio, float *lam_partials,
+    StepArgs a, float lam_scale, int kflags, int prio, float *lam_partials,
     int lam_stride)
 {
     adjoint_strip_body<R, 28, true>(v_all, u_all, an_all, ac_all, ap_all, mask_all, H, W, nstrip,
-                                    per_img, nitems, a, il3, lam_scale, kflags, prio, lam_partials,
+                                    per_img, nitems, a, lam_scale, kflags, prio, lam_partials,
                                     lam_stride);
 }
 
@@ -871,13 +867,13 @@ struct RevStep {
 };
 
 template <int R>
-static hipError_t launch_rev_tile(const RevStep &t, const StepArgs &a, float il3, float ls,
+static hipError_t launch_rev_tile(const RevStep &t, const StepArgs &a, float ls,
                                   hipStream_t s)
 {
     const int nbx = (t.W + kAdjTW - 1) / kAdjTW;
     const int tpi = adjoint_tiles_per_image(t.H, t.W);
     hipLaunchKernelGGL((adjoint_a_kernel<R>), dim3((unsigned)(tpi * t.B)), dim3(256), 0, s, t.u,
-                       t.an, t.mask, t.H, t.W, nbx, tpi, a, il3, ls, t.qx, t.qy, t.pr, t.lp,
+                       t.an, t.mask, t.H, t.W, nbx, tpi, a, ls, t.qx, t.qy, t.pr, t.lp,
                        t.ls);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -902,7 +898,7 @@ static long long resident_waves(K k)
 }
 
 template <int R, int ROWS>
-static hipError_t launch_rev_strip(const RevStep &t, const StepArgs &a, float il3, float ls,
+static hipError_t launch_rev_strip(const RevStep &t, const StepArgs &a, float ls,
                                    hipStream_t s)
 {
     using G = AdjStripGeo<R, ROWS>;
@@ -915,13 +911,13 @@ static hipError_t launch_rev_strip(const RevStep &t, const StepArgs &a, float il
     static const long long cap = resident_waves(adjoint_strip_kernel<R, ROWS>);
     const int prio = nitems <= cap ? 1 : 0;
     hipLaunchKernelGGL((adjoint_strip_kernel<R, ROWS>), dim3(nblk), dim3(256), 0, s, t.v, t.u, t.an,
-                       t.ac, t.ap, t.mask, t.H, t.W, nstrip, per_img, (int)nitems, a, il3, ls,
+                       t.ac, t.ap, t.mask, t.H, t.W, nstrip, per_img, (int)nitems, a, ls,
                        t.kflags(), prio, t.lp, t.ls);
     return hipGetLastError();
 }
 
 template <int R>
-static hipError_t launch_rev_model(const RevStep &t, const StepArgs &a, float il3, float ls,
+static hipError_t launch_rev_model(const RevStep &t, const StepArgs &a, float ls,
                                    hipStream_t s)
 {
     using G = AdjStripGeo<R, 28>;
@@ -933,39 +929,39 @@ static hipError_t launch_rev_model(const RevStep &t, const StepArgs &a, float il
     static const long long cap = resident_waves(adjoint_strip_model_kernel<R>);
     const int prio = nitems <= cap ? 1 : 0;
     hipLaunchKernelGGL((adjoint_strip_model_kernel<R>), dim3(nblk), dim3(256), 0, s, t.v, t.u, t.an,
-                       t.ac, t.ap, t.mask, t.H, t.W, nstrip, per_img, (int)nitems, a, il3, ls,
+                       t.ac, t.ap, t.mask, t.H, t.W, nstrip, per_img, (int)nitems, a, ls,
                        t.kflags(), prio, t.lp, t.ls);
     return hipGetLastError();
 }
 
 template <int R>
-static hipError_t launch_rev_r(const RevStep &t, const StepArgs &a, float il3, float ls,
+static hipError_t launch_rev_r(const RevStep &t, const StepArgs &a, float ls,
                                hipStream_t s)
 {
     // tensor variants: one kernel shape (strips of >= 28 rows)
     if (a.model != 0)
-        return t.shape == kShapeStripShort ? launch_rev_model<R>(t, a, il3, ls, s)
+        return t.shape == kShapeStripShort ? launch_rev_model<R>(t, a, ls, s)
                                            : hipErrorInvalidValue;
     switch (t.shape) {
     case kShapeStrip:
-    case kShapeStripWide: return launch_rev_strip<R, 80>(t, a, il3, ls, s);
-    case kShapeStripTall: return launch_rev_strip<R, 136>(t, a, il3, ls, s);
+    case kShapeStripWide: return launch_rev_strip<R, 80>(t, a, ls, s);
+    case kShapeStripTall: return launch_rev_strip<R, 136>(t, a, ls, s);
     case kShapeStripShort:
-    case kShapeStripWideShort: return launch_rev_strip<R, 28>(t, a, il3, ls, s);
-    case kShapeStripTiny: return launch_rev_strip<R, 8>(t, a, il3, ls, s);
-    default: return launch_rev_tile<R>(t, a, il3, ls, s);
+    case kShapeStripWideShort: return launch_rev_strip<R, 28>(t, a, ls, s);
+    case kShapeStripTiny: return launch_rev_strip<R, 8>(t, a, ls, s);
+    default: return launch_rev_tile<R>(t, a, ls, s);
     }
 }
 
-// One reverse step k (alpha_k, lambda scale -alpha_k tau).
+// One reverse step k (alpha_k; the pixels' s de/ds sum to dL/dlambda with the
+// scale alpha_k tau / lambda).
 static hipError_t launch_reverse_step(const RevStep &t, const eed4_params *p, int k,
                                       hipStream_t s)
 {
     const StepArgs a = make_args(p->sigma, t.R, p->tau, p->lambda, k, model_of_flags(p->flags));
-    const float il3 = (float)(1.0 / ((double)p->lambda * p->lambda * p->lambda));
-    const float ls = -a.alpha * a.tau;
+    const float ls = (float)((double)a.alpha * a.tau / p->lambda);
     const int R = t.R;
-#define EED4_CALL_REV(r) launch_rev_r<r>(t, a, il3, ls, s)
+#define EED4_CALL_REV(r) launch_rev_r<r>(t, a, ls, s)
     EED4_RSWITCH(EED4_CALL_REV)
 #undef EED4_CALL_REV
     return hipErrorInvalidValue;
