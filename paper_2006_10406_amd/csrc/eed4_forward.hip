@@ -84,6 +84,7 @@ __device__ __forceinline__ void strip_kernel_body(const float *ucur, const float
     s.alpha = a.alpha;
     s.il2q = 0.25f * a.inv_lam2;
     s.model = a.model;
+    s.up = kStripAlternate(ROWS) ? seg & 1 : 0;
     strip_step<R, RES, ROWS, CPL, GEN, VST>(lds + wave * G::LDS, s, a.w,
                                             RES ? partials + 2 * (size_t)item : nullptr);
 }
@@ -166,11 +167,8 @@ __global__ __launch_bounds__(256) void blur_kernel(const float *u_all, float *v_
         const int r = k / TW, c = k - r * TW;
         const int y = y0 + r, x = x0 + c;
         if (y >= H || x >= W) continue;
-        const float *colp = sx + r * TW + c;
-        float acc = a.w[0] * colp[0];
-#pragma unroll
-        for (int j = 1; j <= 2 * R; ++j) acc = fmaf(a.w[j], colp[j * TW], acc);
-        v[(size_t)y * W + x] = acc;
+        const float *colp = sx + (r + R) * TW + c;
+        v[(size_t)y * W + x] = ypass_sym<R>(a.w, [&](int j) { return colp[j * TW]; });
     }
 }
 

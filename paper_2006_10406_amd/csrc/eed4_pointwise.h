@@ -31,6 +31,22 @@ __device__ __forceinline__ float mixed_diff(float pp, float mm, float pm, float 
     return 0.25f * ((pp + mm) - (pm + mp));
 }
 
+// The y pass of the Gaussian presmoothing (Sec. 3.1, K_sigma) at one pixel
+// from the x-pass values of its column, at(j) = the value j rows below it
+// (j = -R..R): the centre first, then the pairs at distance 1, 2, ..., R
+// (the sampled kernel is symmetric, w[R - j] = w[R + j]).  The operations do
+// not depend on which end of the column is read first, so strips that stream
+// down or up, tiles and the presmoothing kernel agree bitwise.
+template <int R, typename At>
+__device__ __forceinline__ float ypass_sym(const float *w, At at)
+{
+#pragma clang fp contract(off)
+    float acc = w[R] * at(0);
+#pragma unroll
+    for (int j = 1; j <= R; ++j) acc = fmaf(w[R + j], at(-j) + at(j), acc);
+    return acc;
+}
+
 // Squared norm of twice the regularised gradient: gxs, gys are the central
 // differences v(x+1) - v(x-1), v(y+1) - v(y-1) of the presmoothed image
 // (2 grad u_sigma, Sec. 3.1).

@@ -98,6 +98,7 @@ struct StripArgs {
     int H, W, X0, Y0;
     float tau, alpha, il2q;     // il2q = 1 / (4 lambda^2)
     int model;                  // tensor variant (GEN kernels only)
+    int up;                     // stream the segment bottom up (see strip_step)
 };
 
 // mu1 = g(x) and mu3 of the tensor variants, x = (s/lambda)^2: the
@@ -193,6 +194,20 @@ __device__ __forceinline__ float right_of(const float (&x)[CPL], int q)
 // covering nb = min(H - b0, NROW) rows, so a row offset is one 32-bit scalar
 // (the library keeps NROW * W * 4 below 2^31) and the per-lane column offsets
 // stay fixed for the whole strip.
+// Direction: with segments of >= 64 rows, callers stream odd segments bottom
+// up and even ones top down, so the 2h rows two neighbouring segments share
+// are read by both at nearly the same time (near the end of both streams, or
+// near the start of both) and the second read usually hits in L2; with every
+// segment streaming down, one reads them first and the other last, a whole
+// launch later.  (Measured at 4096^2 and 8192^2: the 64-row strips as fast in
+// the cache-resident case and 5 % faster out of it; 28-row strips 8 % slower,
+// so they all stream down.)  The stencils
+// are symmetric in y: streaming up only negates the y-odd quantities (G_y,
+// u_xy, T_xy and its x differences) exactly, and the y pass is symmetric, so
+// u^{k+1} (and the kept v) are bitwise those of the downward stream; only the
+// FP64 residual partials add the rows in the other order.
+constexpr bool kStripAlternate(int rows) { return rows >= 64; }
+
 template <int R, bool RES, int ROWS = 64, int CPL = 1, bool GEN = false, bool VST = false>
 __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
                                            const float (&w)[2 * kRMax + 1], double *partial)
@@ -204,7 +219,9 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
     const unsigned W4 = 4u * (unsigned)W;
     if constexpr (kLdsSentinel) sentinel_fill_wave(ring, G::LDS);
 
-    const int ybase = s.Y0 - G::h;                            // image row of stream row 0
+    const int ybase = s.Y0 - G::h;                            // top streamed row
+    const int dir = s.up ? -1 : 1;                            // image rows per stream row
+    const int ystart = s.up ? ybase + G::NROW - 1 : ybase;    // image row of stream row 0
     const int b0 = ybase > 0 ? ybase : 0;
     const int nb = (H - b0 < G::NROW) ? H - b0 : G::NROW;
     const size_t base = (size_t)b0 * W;
@@ -253,8 +270,9 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
 
     // the next row to prefetch: its mirrored image row and the output row it serves
     RowTrack ty;
-    ty.init(ybase, H);
-    int on = ybase - R - 2;
+    ty.init(ystart, H);
+    if (s.up) ty.dir = -ty.dir;
+    int on = ystart - dir * (R + 2);
 
     // Loads run two stream rows ahead, always in the same order, so waiting
     // for one row never waits for a later row's loads.
@@ -273,7 +291,7 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
             if constexpr (RES) r.rf[q] = buf_f32(rs_r, vo4[q], ro * W4);
         }
         ty.next(H);
-        ++on;
+        on += dir;
     };
     StripRow<CPL> r0, r1;
     r0.b = r1.b = 0.0f;
@@ -334,13 +352,11 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
             stage_xpass(cur, (2 * R + ph) % D, (2 * R + ph) % P);   // constants once unrolled
 
             // ---- S2: y pass at stream row i - R ----
+            // stream row i - R + j is in slot (ph + R + j) % P
             float v[CPL];
 #pragma unroll
-            for (int q = 0; q < CPL; ++q) {
-                v[q] = w[0] * win[q][ph % P];
-#pragma unroll
-                for (int j = 1; j <= 2 * R; ++j) v[q] = fmaf(w[j], win[q][(ph + j) % P], v[q]);
-            }
+            for (int q = 0; q < CPL; ++q)
+                v[q] = ypass_sym<R>(w, [&](int j) { return win[q][(ph + R + j) % P]; });
 
             // ---- S3: gradient, tensor, Hessian, contraction at row g = i - R - 1 ----
             // (the first rows of the loop produce values that only feed unstored rows)
@@ -378,8 +394,8 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
             float z[CPL];
 #pragma unroll
             for (int q = 0; q < CPL; ++q) z[q] = right_of(txy, q) - left_of(txy, q);
-            const int o = ybase + i - R - 2;
-            if (i >= 2 * G::h && o < H) {      // first output row of the segment is Y0
+            const int o = ystart + dir * (i - R - 2);
+            if (i >= 2 * G::h && o < H) {      // first output row: Y0 (down), Y0 + OH - 1 (up)
                 const unsigned ro = (unsigned)(o - b0) * W4;
 #pragma unroll
                 for (int q = 0; q < CPL; ++q) {

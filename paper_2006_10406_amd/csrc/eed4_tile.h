@@ -185,10 +185,7 @@ __device__ __forceinline__ void step_tile(float *smem, const float *ucur, const 
 #pragma unroll
         for (int e = 0; e < G::NYR; ++e) {
             if (r0 + e < G::VH) {
-                float s = w[0] * win[e];
-#pragma unroll
-                for (int j = 1; j <= 2 * R; ++j) s = fmaf(w[j], win[e + j], s);
-                sV[(r0 + e) * G::XW + c] = s;
+                sV[(r0 + e) * G::XW + c] = ypass_sym<R>(w, [&](int j) { return win[e + R + j]; });
             }
         }
     }
