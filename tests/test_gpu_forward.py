@@ -274,6 +274,28 @@ def test_strip_and_tile_kernels_agree_bitwise():
     assert np.array_equal(outs[0], outs[1])
 
 
+@pytest.mark.parametrize("H,W,sigma", [(148, 61, 2.0), (150, 70, 2.0), (160, 130, 1.0),
+                                         (200, 66, 0.0), (300, 40, 2.6)])
+def test_strips_streaming_up_agree_bitwise(H, W, sigma):
+    # strips of >= 64 rows stream their odd segments bottom up (the last one from beyond
+    # the bottom edge, mirrored, when the segment count is even); every value must equal
+    # the tile kernel's, which does not stream at all
+    announce(f"up/down strip segments vs tiles, {H}x{W}, sigma={sigma}")
+    pr = make_problem(H, W, 6, True, 0.01, 0.05, 950 + H)
+    outs = {}
+    for shape in (0, 3, 4, 7):
+        u = to_dev(pr["u_init"])
+        st, hist = eed4.eed4_inpaint(u, to_dev(pr["mask"]), to_dev(pr["known"]),
+                                     eed4.params(0.03, sigma, 0.05, 7, 3,
+                                                 flags=eed4.EED4_FORCE_SHAPE(shape)),
+                                     history=True)
+        outs[shape] = (u.cpu().numpy(), hist)
+    for shape in (3, 4, 7):
+        assert np.array_equal(outs[shape][0], outs[0][0]), eed4.SHAPE_NAMES[shape]
+        # the FP64 residual partials add rows in another order: equal to rounding only
+        np.testing.assert_allclose(outs[shape][1], outs[0][1], rtol=1e-12, atol=0)
+
+
 @pytest.mark.parametrize("H,W,B", [(300, 260, 1), (96, 80, 4)])
 def test_every_step_shape_and_the_autotuned_default(H, W, B):
     announce(f"all step shapes and the autotuned default, {B} x {H}x{W}")
