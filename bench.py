@@ -72,7 +72,10 @@ def kernel_name(shape_name, R):
 
 
 KERNEL_SOURCES = ("paper_2006_10406_amd/csrc/eed4_strip.h",
-                  "paper_2006_10406_amd/csrc/eed4_forward.hip")
+                  "paper_2006_10406_amd/csrc/eed4_forward.hip",
+                  "paper_2006_10406_amd/csrc/eed4_tile.h",
+                  "paper_2006_10406_amd/csrc/eed4_pointwise.h",
+                  "paper_2006_10406_amd/csrc/eed4_internal.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_large4096_traffic.json")
 
 
