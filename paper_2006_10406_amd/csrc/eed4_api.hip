@@ -356,11 +356,14 @@ int tune_single_step(const eed4_params *p, int B, int H, int W, float *S, float 
     const int R = eed4_radius(p->sigma);
     const StepArgs a = make_args(p->sigma, R, p->tau, p->lambda, 0);
     int order[kNumShapes];
-    const int nc = tune_candidates(default_step_shape(R, B, H, W), order);
+    const int first = default_step_shape(R, B, H, W);
+    const int nc = tune_candidates(first, order);
+    float margins[kNumShapes];
+    for (int i = 0; i < nc; ++i) margins[i] = tune_margin(first, order[i]);
     const int rc = tune_pick(
         order, nc, s, [](int) { return (int)EED4_OK; },
         [&](int sh) { return launch_step(R, sh, S, S, X, nullptr, mask, B, H, W, a, nullptr, s); },
-        "step autotune", shape, nullptr);
+        "step autotune", shape, nullptr, margins);
     if (rc != EED4_OK) return rc;
     tune_remember(single_tune_key(R, B, H, W), *shape);
     return EED4_OK;

@@ -93,7 +93,7 @@ __device__ __forceinline__ void bstrip_body(const BImage *imgs, const BItem *que
         s.alpha = a.alpha;
         s.il2q = 0.25f * __int_as_float(uni(__float_as_int(d.inv_lam2)));
         s.model = a.model;
-        s.up = kStripAlternate(ROWS) ? uni(t.iy) & 1 : 0;   // as in the single-image kernels
+        s.up = strip_alternates(ROWS) ? uni(t.iy) & 1 : 0;   // as in the single-image kernels
         strip_step<R, RES, ROWS, CPL, GEN>(lds + wave * G::LDS, s, a.w,
                                            partials + 2 * (size_t)uni(t.slot));
     }

@@ -84,7 +84,7 @@ __device__ __forceinline__ void strip_kernel_body(const float *ucur, const float
     s.alpha = a.alpha;
     s.il2q = 0.25f * a.inv_lam2;
     s.model = a.model;
-    s.up = kStripAlternate(ROWS) ? seg & 1 : 0;
+    s.up = strip_alternates(ROWS) ? seg & 1 : 0;
     strip_step<R, RES, ROWS, CPL, GEN, VST>(lds + wave * G::LDS, s, a.w,
                                             RES ? partials + 2 * (size_t)item : nullptr);
 }

@@ -97,6 +97,21 @@ inline int tune_candidates(int first, int (&order)[kNumShapes])
 }
 int default_step_shape(int R, int B, int H, int W);
 
+// Margin a candidate of the single-image tuner must beat the current choice
+// by.  Where the default is the 64-row strip (images large enough for it),
+// the 28-row strips, which fetch the halo rows their neighbours share again
+// (1.20x the algorithmic bytes against 1.006x for the 64-row strips, whose
+// segments alternate direction), have to be clearly faster: in sustained
+// runs at 4096^2 they are level with the 64-row strip or a few percent
+// slower, and slower once the image leaves the Infinity Cache, while a short
+// tuning burst has at times put them 2 % ahead.
+constexpr float kTuneMarginRefetch = 0.95f;
+inline float tune_margin(int first, int shape)
+{
+    const bool refetch = shape == kShapeStripShort || shape == kShapeStripWideShort;
+    return first == kShapeStrip && refetch ? kTuneMarginRefetch : kTuneMargin;
+}
+
 // Chooses one of n candidate shapes (cands[0] the default) by timing on stream
 // s.  prepare(shape) sets up a candidate outside the timed region (EED4 code);
 // launch(shape) enqueues one launch of it.  Every candidate is sampled in two
@@ -105,11 +120,11 @@ int default_step_shape(int R, int B, int H, int W);
 // clock ramp at the start of tuning does not favour the candidates timed later
 // and a fixed cost per launch (e.g. a profiler's) does not decide between
 // shapes a few percent apart.  A candidate replaces the current choice only
-// when it is faster by more than kTuneMargin.
+// when it is faster by more than kTuneMargin (or its own entry of margins).
 constexpr int kTuneLaunches = 4;
 template <typename Prepare, typename Launch>
 int tune_pick(const int *cands, int n, hipStream_t s, Prepare &&prepare, Launch &&launch,
-              const char *where, int *best, float *best_ms)
+              const char *where, int *best, float *best_ms, const float *margins = nullptr)
 {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
@@ -137,7 +152,7 @@ int tune_pick(const int *cands, int n, hipStream_t s, Prepare &&prepare, Launch 
     if (e != hipSuccess) return hip_fail(e, where);
     int b = 0;
     for (int i = 1; i < n; ++i)
-        if (tmin[i] < kTuneMargin * tmin[b]) b = i;
+        if (tmin[i] < (margins ? margins[i] : kTuneMargin) * tmin[b]) b = i;
     *best = cands[b];
     if (best_ms) *best_ms = tmin[b];
     return EED4_OK;

@@ -194,6 +194,7 @@ __device__ __forceinline__ float right_of(const float (&x)[CPL], int q)
 // covering nb = min(H - b0, NROW) rows, so a row offset is one 32-bit scalar
 // (the library keeps NROW * W * 4 below 2^31) and the per-lane column offsets
 // stay fixed for the whole strip.
+//
 // Direction: with segments of >= 64 rows, callers stream odd segments bottom
 // up and even ones top down, so the 2h rows two neighbouring segments share
 // are read by both at nearly the same time (near the end of both streams, or
@@ -201,12 +202,12 @@ __device__ __forceinline__ float right_of(const float (&x)[CPL], int q)
 // segment streaming down, one reads them first and the other last, a whole
 // launch later.  (Measured at 4096^2 and 8192^2: the 64-row strips as fast in
 // the cache-resident case and 5 % faster out of it; 28-row strips 8 % slower,
-// so they all stream down.)  The stencils
-// are symmetric in y: streaming up only negates the y-odd quantities (G_y,
-// u_xy, T_xy and its x differences) exactly, and the y pass is symmetric, so
-// u^{k+1} (and the kept v) are bitwise those of the downward stream; only the
-// FP64 residual partials add the rows in the other order.
-constexpr bool kStripAlternate(int rows) { return rows >= 64; }
+// so they all stream down.)  The stencils are symmetric in y: streaming up
+// only negates the y-odd quantities (G_y, u_xy, T_xy and its x differences)
+// exactly, and the y pass is symmetric, so u^{k+1} (and the kept v) are
+// bitwise those of the downward stream; only the FP64 residual partials add
+// the rows in the other order.
+constexpr bool strip_alternates(int rows) { return rows >= 64; }
 
 template <int R, bool RES, int ROWS = 64, int CPL = 1, bool GEN = false, bool VST = false>
 __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
