@@ -14,21 +14,34 @@
 
 namespace eed4 {
 
-// Second differences of u (Sec. 3.3 stencils): centre c, neighbours a and b on
-// one axis.
+// Second differences of u (Sec. 3.3 stencils): centre c and the sum of its
+// two neighbours on one axis, a + b (taken in that order), ...
+__device__ __forceinline__ float second_diff_sum(float ab, float c)
+{
+#pragma clang fp contract(off)
+    return fmaf(-2.0f, c, ab);
+}
+// ... or the neighbours a and b themselves.
 __device__ __forceinline__ float second_diff(float a, float c, float b)
 {
 #pragma clang fp contract(off)
-    return fmaf(-2.0f, c, a + b);
+    return second_diff_sum(a + b, c);
+}
+
+// Central x difference along one row, u(x+1) - u(x-1).
+__device__ __forceinline__ float xdiff(float left, float right)
+{
+#pragma clang fp contract(off)
+    return right - left;
 }
 
 // Mixed difference u_xy with the signs of a derivative (Sec. 3.3 prints four
-// plus signs): pp = u(y+1, x+1), mm = u(y-1, x-1), pm = u(y+1, x-1),
-// mp = u(y-1, x+1).
-__device__ __forceinline__ float mixed_diff(float pp, float mm, float pm, float mp)
+// plus signs), from the x differences of the rows below and above:
+// dp = u(y+1, x+1) - u(y+1, x-1), dm = u(y-1, x+1) - u(y-1, x-1).
+__device__ __forceinline__ float mixed_diff(float dp, float dm)
 {
 #pragma clang fp contract(off)
-    return 0.25f * ((pp + mm) - (pm + mp));
+    return 0.25f * (dp - dm);
 }
 
 // The y pass of the Gaussian presmoothing (Sec. 3.1, K_sigma) at one pixel

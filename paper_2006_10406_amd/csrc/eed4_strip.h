@@ -301,6 +301,18 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
     prefetch(r0);
     prefetch(r1);
 
+    // The Hessian of u at row g needs u(x-1), u(x), u(x+1) at rows g-1, g, g+1.
+    // With segments of >= 64 rows (about 4 waves per SIMD, registers to spare)
+    // they are kept per staged row, as u(x), u(x-1) + u(x+1) and u(x+1) - u(x-1),
+    // in registers indexed like the ring (slot i % D), from the x-pass taps
+    // R-1, R, R+1 of row i; the shorter strips, which need 8 waves per SIMD,
+    // read them back from the ring.
+    constexpr bool HREG = CPL == 1 && ROWS >= 64;
+    constexpr int HD = HREG ? D : 1;
+    float hc[HD], hs[HD], hd[HD];
+#pragma unroll
+    for (int j = 0; j < HD; ++j) hc[j] = hs[j] = hd[j] = 0.0f;
+
     // stage one row of u^k into ring row rr and take its x pass into window slot ws
     auto stage_xpass = [&](const StripRow<CPL> &cur, int rr, int ws) {
 #pragma unroll
@@ -313,6 +325,12 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
 #pragma unroll
             for (int j = 1; j <= 2 * R; ++j) acc = fmaf(w[j], col[(q + j) * CS + rr], acc);
             win[q][ws] = acc;
+        }
+        if constexpr (HREG) {
+            const float l = col[(R - 1) * CS + rr], c = col[R * CS + rr], r = col[(R + 1) * CS + rr];
+            hc[rr] = c;
+            hs[rr] = l + r;
+            hd[rr] = xdiff(l, r);
         }
     };
 
@@ -367,14 +385,24 @@ __device__ __forceinline__ void strip_step(float *ring, const StripArgs &s,
                 vo[q] = v_m2[q];                                              // v at row g - 1
                 const float gxs = right_of(v_m1, q) - left_of(v_m1, q);      // 2 gx
                 const float gys = v[q] - v_m2[q];                             // 2 gy
-                // column q of this lane is staged column CPL l + q + R; rows g-1, g, g+1
-                const float *um = col + (q + R) * CS + (R - 2 + ph + D) % D;
-                const float *u0 = col + (q + R) * CS + (R - 1 + ph + D) % D;
-                const float *up = col + (q + R) * CS + (R + ph) % D;
-                uc[q] = u0[0];
-                const float hxx = second_diff(u0[-CS], uc[q], u0[CS]);
-                const float hyy = second_diff(um[0], uc[q], up[0]);
-                const float hxy = mixed_diff(up[CS], um[-CS], up[-CS], um[CS]);
+                // rows g-1, g, g+1 are in ring slots sm, sg, sp
+                const int sm = (R - 2 + ph + D) % D, sg = (R - 1 + ph + D) % D, sp = (R + ph) % D;
+                float hxx, hyy, hxy;
+                if constexpr (HREG) {
+                    uc[q] = hc[sg];
+                    hxx = second_diff_sum(hs[sg], uc[q]);
+                    hyy = second_diff(hc[sm], uc[q], hc[sp]);
+                    hxy = mixed_diff(hd[sp], hd[sm]);
+                } else {
+                    // column q of this lane is staged column CPL l + q + R
+                    const float *um = col + (q + R) * CS + sm;
+                    const float *u0 = col + (q + R) * CS + sg;
+                    const float *up = col + (q + R) * CS + sp;
+                    uc[q] = u0[0];
+                    hxx = second_diff(u0[-CS], uc[q], u0[CS]);
+                    hyy = second_diff(um[0], uc[q], up[0]);
+                    hxy = mixed_diff(xdiff(up[-CS], up[CS]), xdiff(um[-CS], um[CS]));
+                }
 
                 const float s2 = grad2_sq(gxs, gys);                          // 4 |grad|^2
                 float mu1, mu3;

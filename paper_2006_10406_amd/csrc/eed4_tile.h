@@ -206,7 +206,8 @@ __device__ __forceinline__ void step_tile(float *smem, const float *ucur, const 
             const float uc = u[0];
             const float hxx = second_diff(u[-1], uc, u[1]);
             const float hyy = second_diff(u[-G::UW], uc, u[G::UW]);
-            const float hxy = mixed_diff(u[G::UW + 1], u[-G::UW - 1], u[G::UW - 1], u[-G::UW + 1]);
+            const float hxy = mixed_diff(xdiff(u[G::UW - 1], u[G::UW + 1]),
+                                         xdiff(u[-G::UW - 1], u[-G::UW + 1]));
             const float s2 = grad2_sq(gxs, gys);                     // 4 |grad|^2
             float mu1, mu3;
             foeed_mu(s2, il2q, mu1, mu3);
