@@ -499,6 +499,21 @@ __device__ __forceinline__ void adjoint_strip_step(float *lds, const AdjStripArg
     RowTrack ty;                      // next prefetch: its mirrored image row
     ty.init(ybase, H);
     int on = ybase - h;                                       // output row it serves
+    // ubar^{k+1} and the mask at output row o are those the stream read at its
+    // row o, h rows earlier (same column on output lanes, no mirroring inside
+    // the image).  Where the unrolled row block covers h + 1 rows (R >= 2) they
+    // are kept in registers indexed by stream row % U instead of being loaded
+    // again: by then the rows have left L2 (about 5 of the 22 bytes a pixel
+    // otherwise fetches).
+    constexpr bool OREG = U >= h + 1;
+    constexpr int OQ = OREG ? U : 1;
+    float rnq[OQ];
+    unsigned rmq[OQ];
+#pragma unroll
+    for (int j = 0; j < OQ; ++j) {
+        rnq[j] = 0.0f;
+        rmq[j] = 0u;
+    }
     auto prefetch = [&](AdjStripRow &r) {
         const unsigned sr = (unsigned)((ty.y > b0 ? ty.y : b0) - b0);
         r.v = buf_f32(rs_v, 4u * cm, sr * W4);
@@ -508,13 +523,17 @@ __device__ __forceinline__ void adjoint_strip_step(float *lds, const AdjStripArg
         int oc = on < b0 ? b0 : on;                           // clamped; unused rows are not stored
         oc = oc > H - 1 ? H - 1 : oc;
         const unsigned ro = (unsigned)(oc - b0);
-        r.oa = buf_f32(rs_an, vo4, ro * W4);
+        if constexpr (!OREG) {
+            r.oa = buf_f32(rs_an, vo4, ro * W4);
+            r.omk = __builtin_amdgcn_raw_buffer_load_b8(rs_m, vo1, ro * (unsigned)W, 0);
+        }
         r.oc = buf_f32(rs_acl, vo4, ro * W4);
-        r.omk = __builtin_amdgcn_raw_buffer_load_b8(rs_m, vo1, ro * (unsigned)W, 0);
         ty.next(H);
         ++on;
     };
     AdjStripRow r0, r1;
+    r0.oa = r1.oa = 0.0f;
+    r0.omk = r1.omk = 0u;
     prefetch(r0);
     prefetch(r1);
 
@@ -540,6 +559,10 @@ __device__ __forceinline__ void adjoint_strip_step(float *lds, const AdjStripArg
             const AdjStripRow cur = r0;
             r0 = r1;
             prefetch(r1);
+            if constexpr (OREG) {
+                rnq[ph] = cur.rn;                                    // stream row i % U = ph
+                rmq[ph] = cur.rmk;
+            }
 
             // ---- S3 at row g = i - 1 (rows g-1, g, g+1: m2, m1, this row) ----
             const float v_p1 = cur.v, u_p1 = cur.u;
@@ -604,8 +627,9 @@ __device__ __forceinline__ void adjoint_strip_step(float *lds, const AdjStripArg
                 for (int j = 0; j <= 2 * R; ++j)
                     cq = fmaf(w[j], dwin[((ph - h - R + j) % P + P) % P], cq);
                 const float pro = prr[((ph - h) % P + P) % P * 64];
-                const float anv = cur.oa;
-                const bool mk = cur.omk != 0;
+                const int so = ((ph - h) % U + U) % U;              // stream row i - h
+                const float anv = OREG ? rnq[so] : cur.oa;
+                const bool mk = (OREG ? rmq[so] : cur.omk) != 0;
                 const float rv = mk ? 0.0f : anv;
                 float acv = fmaf(s.alpha, fmaf(-s.tau, pro + cq, rv), cur.oc);
                 const float back = (1.0f - s.alpha) * rv;
