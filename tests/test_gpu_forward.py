@@ -275,7 +275,8 @@ def test_strip_and_tile_kernels_agree_bitwise():
 
 
 @pytest.mark.parametrize("H,W,sigma", [(148, 61, 2.0), (150, 70, 2.0), (160, 130, 1.0),
-                                         (200, 66, 0.0), (300, 40, 2.6)])
+                                         (200, 66, 0.0), (300, 40, 2.6), (170, 50, 0.3),
+                                         (190, 90, 1.3), (260, 45, 2.3)])
 def test_strips_streaming_up_agree_bitwise(H, W, sigma):
     # strips of >= 64 rows stream their odd segments bottom up (the last one from beyond
     # the bottom edge, mirrored, when the segment count is even); every value must equal
