@@ -1280,6 +1280,9 @@ extern "C" int eed4_backward(const float *ckpt, const uint8_t *mask, const float
         }
     }
 #undef EED4_TRY2
+    // on an error the recompute stream may still hold queued work on the
+    // caller's workspace: let it finish before the caller can free it
+    if (rc2 != EED4_OK) (void)hipStreamSynchronize(s1);
     for (auto &x : ev) (void)hipEventDestroy(x);
     if (rc2 != EED4_OK) return rc2;
     EED4_TRY(launch_adjoint_final(an, mask, grad_known, grad_init, N, s), "final");
